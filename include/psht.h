@@ -1,0 +1,194 @@
+/*
+ * psht -- partial-sky spin-weighted spherical harmonic transforms on MI355X.
+ *
+ * C ABI of libpsht.so.  Plain pointers and sizes only; every device pointer
+ * is a HIP device allocation on the current device, every stream a
+ * hipStream_t passed as void* (NULL = the legacy default stream).
+ *
+ * The library computes, for coefficients g_lm, c_lm (l <= lmax) and spin s,
+ *
+ *   Synthesis general (Carron & Reinecke, Sec. I, eq. syn):
+ *     f_p = - sum_{l,m} (g_lm + i c_lm) sY_lm(theta_p, phi_p),
+ *   Adjoint synthesis general (Sec. I):
+ *     g~_lm = -1/2    sum_p [ f_p sY*_lm + (-1)^s conj(f_p) (-s)Y*_lm ],
+ *     c~_lm = -1/(2i) sum_p [ f_p sY*_lm - (-1)^s conj(f_p) (-s)Y*_lm ],
+ *
+ * with sY_lm = sqrt((2l+1)/4pi) d^l_{m,-s}(theta) e^{i m phi} (Appendix A,
+ * eq. Ylm) and the reality condition a*_lm = (-1)^m a_l,-m (Sec. I).  It
+ * follows the partial-sky method of Sec. II: rings inside the apodized cap
+ * theta <= theta_max = theta*(1 + eps_apo) (steps 1-2), the weighted,
+ * stretched map w(Theta) f(Theta theta_max / pi, phi) (step 3), Lmax + 1
+ * rings and the Fourier-sphere evaluation at the points (step 4, Sec. I.B),
+ * with the window and apodization rules of Sec. II.B-C (summary paragraph).
+ *
+ * Layouts
+ *   alm  : complex, [nmaps][2][nalm], g first then c; nalm = (lmax+1)(lmax+2)/2,
+ *          index(l, m) = m (2 lmax + 1 - m) / 2 + l for 0 <= m <= l.  Always
+ *          complex128 (double).  Entries with l < s are ignored by synthesis
+ *          and written as zero by the adjoint; Im(g_l0), Im(c_l0) are ignored
+ *          by synthesis and written as zero by the adjoint.
+ *   map  : complex, [nmaps][npoints] in the caller's point order; complex128
+ *          for FP64 plans, complex64 for FP32 plans (info.map_is_fp32).
+ *   theta, phi : double [npoints] device arrays, colatitude in [0, pi] and
+ *          longitude (any real, reduced mod 2 pi), in the patch frame, i.e.
+ *          with the patch centre at the north pole (Sec. II, step 1).
+ *
+ * Inner products under which psht_adjoint is the exact adjoint of
+ * psht_synth (up to rounding): maps  <f, f'> = sum_p Re(conj(f_p) f'_p);
+ * coefficients <a, a'> = sum_l (g_l0 g'_l0 + c_l0 c'_l0)
+ *                         + 2 sum_{l, m >= 1} Re(conj(g_lm) g'_lm + conj(c_lm) c'_lm).
+ *
+ * Errors: every argument is validated before anything is launched; on a
+ * non-OK status nothing has been written to the outputs (except for
+ * PSHT_ERR_DEVICE raised by the runtime after launches).  psht_last_error()
+ * returns a thread-local message for the last non-OK status of the calling
+ * thread.  No C++ exception crosses this interface.
+ */
+#ifndef PSHT_H
+#define PSHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psht_plan_s *psht_plan;
+
+typedef enum {
+    PSHT_OK = 0,
+    PSHT_ERR_ARG = 1,          /* invalid argument (value, null pointer, point out of range) */
+    PSHT_ERR_NOMEM = 2,        /* device or host allocation failed */
+    PSHT_ERR_DEVICE = 3,       /* a HIP runtime call failed */
+    PSHT_ERR_UNSUPPORTED = 4,  /* size outside what the kernels handle */
+    PSHT_ERR_WORKSPACE = 5     /* workspace missing or smaller than required */
+} psht_status;
+
+typedef enum {
+    PSHT_PREC_AUTO = 0,  /* FP32 grid/NUFFT when epsilon >= 1e-6, else FP64 */
+    PSHT_PREC_FP32 = 1,
+    PSHT_PREC_FP64 = 2
+} psht_precision;
+
+/* Everything a plan derives from (lmax, spin, points, epsilon).  Names follow
+ * the paper: Lmax is the band limit of the stretched map (eq. Lmax2), eps_apo
+ * the fractional apodization length, alpha the bell shape parameter (summary
+ * of Sec. II.C), theta_max = theta_star (1 + eps_apo) (Sec. II, step 2). */
+typedef struct {
+    int32_t lmax, spin;
+    int32_t Lmax;            /* band limit in Theta; rings j = 0..Lmax */
+    int32_t n2;              /* samples on the doubled circle, 2 Lmax + 1 */
+    int32_t mmax;            /* largest m kept on any ring (polar optimization) */
+    int32_t nufft_w;         /* ES kernel width in grid cells */
+    int32_t ntheta_grid;     /* oversampled NUFFT grid size along Theta */
+    int32_t nphi_grid;       /* oversampled NUFFT grid size along phi */
+    int32_t row_lo;          /* first Theta-grid row touched by any point */
+    int32_t rows_used;       /* number of Theta-grid rows touched by the points */
+    int32_t map_is_fp32;     /* 1: map buffers are complex64 */
+    int32_t full_sky;        /* 1: patch too large, theta_max = pi, w = 1, Lmax >= lmax */
+    double epsilon;
+    double theta_star, theta_min, theta_max, eps_apo, alpha;
+    double nufft_beta, nufft_sigma;
+    double predicted_speedup; /* 1 / ((1 + eps_apo)(1 - cos theta_max)), Sec. II.A */
+    double legendre_triples;  /* sum over rings of (l, m) pairs kept: algorithmic work */
+    int64_t npoints;
+    size_t resident_bytes;          /* device memory the plan holds */
+    size_t workspace_bytes_per_map; /* workspace psht_synth/psht_adjoint need per map */
+} psht_plan_info;
+
+/* Build a plan for npoints points (device arrays theta, phi; read during the
+ * call only, not kept).  Validates lmax >= 0, 0 <= spin <= lmax,
+ * 1e-14 <= epsilon <= 1e-2, npoints >= 0 and < 2^31, every theta in
+ * [0, pi] and every phi finite (checked on the device; one device-to-host
+ * synchronisation on `hip_stream`).  Sorts the points into NUFFT tiles and
+ * uploads rings, window weights, per-ring m cut-offs and kernel tables; the
+ * Legendre recurrence tables are shared by all plans of the same (lmax, spin).
+ * On success *out owns device memory until psht_plan_destroy. */
+psht_status psht_plan_create(psht_plan *out, int lmax, int spin, int64_t npoints,
+                             const double *theta, const double *phi,
+                             double epsilon, int precision, void *hip_stream);
+
+/* Copy the plan's parameters into *info. */
+psht_status psht_plan_query(psht_plan plan, psht_plan_info *info);
+
+/* Synthesis general (eq. syn) of nmaps coefficient sets into nmaps maps,
+ * asynchronously on hip_stream.  alm: device, complex128 [nmaps][2][nalm];
+ * map: device, [nmaps][npoints] complex128 or complex64 (plan precision).
+ * workspace: device buffer of at least nmaps * workspace_bytes_per_map bytes,
+ * caller-owned, not used after the stream reaches the end of the call. */
+psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map,
+                       void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Adjoint synthesis general (Sec. I) of nmaps maps into nmaps coefficient
+ * sets; same layouts and workspace rule as psht_synth.  alm is overwritten. */
+psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm,
+                         void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Free the plan's device memory.  The caller must synchronise every stream
+ * that still runs work of this plan first.  NULL is a no-op. */
+void psht_plan_destroy(psht_plan plan);
+
+/* Thread-local text for the last non-OK status of this thread ("" if none). */
+const char *psht_last_error(void);
+
+/* Host-only evaluation of the plan parameters for a cap of radius theta_star
+ * (theta_min = 0), without any device work: the rules of Sec. II.B-C for
+ * eps_apo, theta_max, Lmax (eq. Lmax2, rounded up so that 2 Lmax + 1 has only
+ * the factors 3, 5, 7, 11, 13), the rings Theta_j = 2 pi j / (2 Lmax + 1),
+ * theta_j = Theta_j theta_max / pi (Sec. II.A), the window weights w_j
+ * (Sec. II.C) and the per-ring m cut-offs.  ring_theta, ring_weight and
+ * ring_mmax are host arrays of `capacity` entries (may be NULL when
+ * capacity is 0); they receive min(capacity, Lmax + 1) rings.  The per-ring
+ * m cut-off search runs only when capacity > 0; with capacity 0, info->mmax
+ * is lmax and info->legendre_triples counts every m on every ring. */
+psht_status psht_plan_geometry(int lmax, int spin, double theta_star, double epsilon, int precision,
+                               psht_plan_info *info, double *ring_theta, double *ring_weight,
+                               int32_t *ring_mmax, int capacity);
+
+/* ---- Stage-level entry points (diagnostics and stage tests) ----------------
+ * Run a single stage of a plan on device buffers.  Layouts:
+ *   PSHT_STAGE_LEGENDRE_SYNTH : in = alm complex128 [2][nalm],
+ *                               out = F complex128 [2 mmax + 1][Lmax + 1],
+ *                               F[(m + mmax)(Lmax+1) + j] = F_m(theta_j), the
+ *                               azimuthal Fourier coefficient of the map of
+ *                               eq. syn on ring j; zero where m is cut off.
+ *   PSHT_STAGE_LEGENDRE_ADJOINT : in = F' (same layout), out = alm [2][nalm];
+ *                               the exact transpose of the stage above.
+ * workspace may be NULL for these stages. */
+enum { PSHT_STAGE_LEGENDRE_SYNTH = 1, PSHT_STAGE_LEGENDRE_ADJOINT = 2 };
+psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, void *hip_stream);
+
+/* Batched complex FFT on device data, the kernel the Theta and phi stages use
+ * (diagnostics and tests): `batch` transforms of length n (factors 2,3,5,7,11,13,
+ * n <= 8192), contiguous rows, in place is allowed.
+ * sign = -1: out_k = sum_j in_j e^{-2 pi i jk/n}; sign = +1: e^{+...}; unnormalized.
+ * fp32 = 1 selects complex64 data. */
+psht_status psht_fft(int n, int batch, int sign, int fp32, const void *in, void *out, void *hip_stream);
+
+/* ---- Per-stage timing ------------------------------------------------------
+ * With timing enabled, every psht_synth / psht_adjoint call on the plan records
+ * a pair of HIP events around each stage launch on the call's stream;
+ * psht_plan_timing synchronises those events and returns, per stage, the
+ * summed elapsed milliseconds and the number of launches since timing was
+ * (re-)enabled.  Stage indices: PSHT_T_* below.  Not thread-safe: one caller
+ * at a time per plan while timing is on. */
+enum {
+    PSHT_T_LEG_SYNTH = 0, PSHT_T_THETA_SYNTH = 1, PSHT_T_PHI_SYNTH = 2, PSHT_T_INTERP = 3,
+    PSHT_T_GRID_ZERO = 4, PSHT_T_SPREAD = 5, PSHT_T_PHI_ADJ = 6, PSHT_T_THETA_ADJ = 7,
+    PSHT_T_ALM_ZERO = 8, PSHT_T_LEG_ADJ = 9, PSHT_T_COUNT = 10
+};
+psht_status psht_plan_set_timing(psht_plan plan, int enable);
+psht_status psht_plan_timing(psht_plan plan, double *ms, int64_t *launches);
+
+/* Host evaluation (diagnostics and tests) of
+ *   lambda+_l = sqrt((2l+1)/4pi) d^l_{m,-s}(theta),  lambda-_l = sqrt((2l+1)/4pi) d^l_{m,s}(theta)
+ * (Appendix A, eq. Ylm) for l = 0..lmax into lam_plus / lam_minus (host arrays
+ * of lmax + 1 doubles), by exactly the seeds, recurrence tables and rescaling
+ * the GPU Legendre kernels use.  Values still below the double range are 0. */
+psht_status psht_legendre_column(int lmax, int spin, int m, double theta, double *lam_plus, double *lam_minus);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSHT_H */

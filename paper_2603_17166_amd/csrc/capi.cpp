@@ -1,0 +1,506 @@
+// C ABI of libpsht (declared in include/psht.h): argument validation, plan
+// construction (point statistics, geometry, tables, point sort), workspace
+// layout and the stage sequences of synthesis and adjoint synthesis.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "leg_common.h"
+#include "psht_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+psht_status fail(psht_status code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+psht_status fail(const psht::Error &e) { return fail(e.code, e.msg); }
+
+psht_status device_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? PSHT_ERR_NOMEM : PSHT_ERR_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename T> bool dalloc(psht_plan_s &p, T *&ptr, size_t count) {
+    void *raw = nullptr;
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&raw, bytes) != hipSuccess) return false;
+    p.allocations.push_back(raw);
+    p.resident += bytes;
+    ptr = static_cast<T *>(raw);
+    return true;
+}
+
+// Synchronous upload: the host vectors are temporaries of plan creation.
+template <typename T> bool upload(psht_plan_s &p, T *&ptr, const std::vector<T> &host, hipStream_t) {
+    if (!dalloc(p, ptr, host.size())) return false;
+    if (host.empty()) return true;
+    return hipMemcpy(ptr, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+void free_plan(psht_plan_s *p) {
+    if (!p) return;
+    for (auto &e : p->pending) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+    for (void *a : p->allocations) (void)hipFree(a);
+    delete p;
+}
+
+hipEvent_t take_event(psht_plan_s &p) {
+    if (!p.event_pool.empty()) {
+        hipEvent_t e = p.event_pool.back();
+        p.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one stage launch, bracketed by timing events when timing is on.
+template <typename Fn> hipError_t timed(psht_plan_s &p, int stage, hipStream_t st, Fn fn) {
+    if (!p.timing) return fn();
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return fn();
+    (void)hipEventRecord(a, st);
+    hipError_t e = fn();
+    (void)hipEventRecord(b, st);
+    p.pending.push_back({stage, {a, b}});
+    return e;
+}
+
+bool make_fft_table(psht_plan_s &p, psht::FftTable &t, int n, hipStream_t st) {
+    if (!psht::fft_factor(n, t.f)) return false;
+    t.n = n;
+    std::vector<double> tw(2 * (size_t)n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < n; ++k) {
+        long double a = 2 * pi * k / n;
+        tw[2 * k] = (double)cosl(a);
+        tw[2 * k + 1] = (double)(-sinl(a));
+    }
+    return upload(p, t.d_tw, tw, st);
+}
+
+void fill_info(const psht_plan_s &p, psht_plan_info *info) {
+    const psht::Geometry &g = p.g;
+    std::memset(info, 0, sizeof(*info));
+    info->lmax = g.lmax;
+    info->spin = g.spin;
+    info->Lmax = g.Lmax;
+    info->n2 = g.N2;
+    info->mmax = g.mmax;
+    info->nufft_w = g.W;
+    info->ntheta_grid = g.Ntheta;
+    info->nphi_grid = g.Nphi;
+    info->row_lo = g.row_lo;
+    info->rows_used = g.rows_used;
+    info->map_is_fp32 = g.fp32 ? 1 : 0;
+    info->full_sky = g.full_sky ? 1 : 0;
+    info->epsilon = g.eps;
+    info->theta_star = g.theta_star;
+    info->theta_min = g.theta_min;
+    info->theta_max = g.theta_max;
+    info->eps_apo = g.eps_apo;
+    info->alpha = g.alpha;
+    info->nufft_beta = g.beta;
+    info->nufft_sigma = g.sigma;
+    info->predicted_speedup = g.predicted_speedup;
+    info->legendre_triples = g.legendre_triples;
+    info->npoints = p.npts;
+    info->resident_bytes = p.resident + (p.leg ? p.leg->bytes : 0);
+    info->workspace_bytes_per_map = p.ws_per_map;
+}
+
+struct ScopedDevFree {
+    void *p = nullptr;
+    ~ScopedDevFree() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
+                             const double *phi, double epsilon, int precision, hipStream_t st) {
+    if (!out) return fail(PSHT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (lmax < 0 || spin < 0 || spin > lmax) return fail(PSHT_ERR_ARG, "need lmax >= 0 and 0 <= spin <= lmax");
+    if (lmax > 16384) return fail(PSHT_ERR_UNSUPPORTED, "lmax above 16384");
+    if (!(epsilon >= 1e-14 && epsilon <= 1e-2)) return fail(PSHT_ERR_ARG, "epsilon must lie in [1e-14, 1e-2]");
+    if (precision < PSHT_PREC_AUTO || precision > PSHT_PREC_FP64) return fail(PSHT_ERR_ARG, "unknown precision");
+    if (npoints < 0 || npoints >= (int64_t(1) << 31)) return fail(PSHT_ERR_ARG, "npoints must lie in [0, 2^31)");
+    if (npoints > 0 && (!theta || !phi)) return fail(PSHT_ERR_ARG, "theta/phi are NULL");
+
+    // theta range and validity (one device-to-host synchronisation)
+    double tmin = 0.0, tmax = 0.0;
+    if (npoints > 0) {
+        ScopedDevFree stats;
+        hipError_t e = hipMalloc(&stats.p, sizeof(double) * 3 * 1024);
+        if (e != hipSuccess) return device_fail(e, "allocating point statistics");
+        e = psht::launch_point_stats(theta, phi, npoints, static_cast<double *>(stats.p), st);
+        if (e != hipSuccess) return device_fail(e, "point statistics kernel");
+        std::vector<double> h(3 * 1024);
+        e = hipMemcpyAsync(h.data(), stats.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(e, "reading point statistics");
+        double mn = 1e300, mx = -1e300, bad = 0;
+        for (int b = 0; b < 1024; ++b) {
+            mn = std::min(mn, h[3 * b]);
+            mx = std::max(mx, h[3 * b + 1]);
+            bad += h[3 * b + 2];
+        }
+        if (bad > 0)
+            return fail(PSHT_ERR_ARG, "some theta outside [0, pi] or phi not finite (" +
+                                          std::to_string((long long)bad) + " points)");
+        tmin = mn;
+        tmax = mx;
+    }
+
+    std::unique_ptr<psht_plan_s, void (*)(psht_plan_s *)> plan(new psht_plan_s(), free_plan);
+    psht_plan_s &p = *plan;
+    p.npts = npoints;
+    psht::Error err;
+    if (!psht::geometry_compute(p.g, lmax, spin, tmax, tmin, epsilon, precision, true, err)) return fail(err);
+    const psht::Geometry &g = p.g;
+    const bool fp32 = g.fp32;
+    const int fmax = fp32 ? psht::kFftMaxLds32 : psht::kFftMaxLds64;
+    if (g.Ntheta > fmax || g.N2 > fmax)
+        return fail(PSHT_ERR_UNSUPPORTED, "Theta grid of " + std::to_string(g.Ntheta) + " exceeds the LDS FFT limit");
+    p.phi_split = g.Nphi > fmax;
+    if (p.phi_split && g.Nphi / 2 > fmax)
+        return fail(PSHT_ERR_UNSUPPORTED, "phi grid of " + std::to_string(g.Nphi) + " exceeds the LDS FFT limit");
+
+    p.leg = psht::leg_table_get(lmax, spin, err);
+    if (!p.leg) return fail(err);
+
+    // rings
+    std::vector<double> ry(g.nring), rch(g.nring), rsh(g.nring);
+    for (int j = 0; j < g.nring; ++j) {
+        long double t = g.ring_theta[j], sh = sinl(t / 2);
+        ry[j] = (double)(2 * sh * sh);
+        rch[j] = (double)cosl(t / 2);
+        rsh[j] = (double)sh;
+    }
+    if (!upload(p, p.d_ring_y, ry, st) || !upload(p, p.d_ring_ch, rch, st) || !upload(p, p.d_ring_sh, rsh, st) ||
+        !upload(p, p.d_ring_w, g.ring_w, st) || !upload(p, p.d_ring_mmax, g.ring_mmax, st))
+        return fail(PSHT_ERR_NOMEM, "uploading ring tables");
+
+    // Legendre work items: `group` chunks of 64 R rings per order m, groups padded to a multiple of 8.
+    {
+        const int chunk = psht::leg_rings_per_item();
+        const int group = (g.nring + chunk - 1) / chunk;
+        int ngroups = ((g.mmax + 1) + 7) / 8 * 8;
+        std::vector<psht::LegItem> items((size_t)ngroups * group, psht::LegItem{0, 0, 0, 0});
+        for (int m = 0; m <= g.mmax; ++m) {
+            int first = -1, last = -1;
+            for (int j = 0; j < g.nring; ++j)
+                if (g.ring_mmax[j] >= m) {
+                    if (first < 0) first = j;
+                    last = j;
+                }
+            for (int c = 0; c < group; ++c) {
+                psht::LegItem &it = items[(size_t)m * group + c];
+                it.m = m;
+                if (first < 0) continue;
+                int jb = first + c * chunk, je = std::min(first + (c + 1) * chunk, last + 1);
+                if (jb < je) {
+                    it.jb = jb;
+                    it.je = je;
+                }
+            }
+        }
+        p.n_leg_items = (int)items.size();
+        p.leg_rings_per_item = chunk;
+        if (!upload(p, p.d_leg_items, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
+    }
+
+    // NUFFT tables
+    if (!upload(p, p.d_psihat_t, g.psihat_theta, st) || !upload(p, p.d_psihat_p, g.psihat_phi, st))
+        return fail(PSHT_ERR_NOMEM, "uploading kernel tables");
+    if (!make_fft_table(p, p.fft_n2, g.N2, st) || !make_fft_table(p, p.fft_nt, g.Ntheta, st) ||
+        !make_fft_table(p, p.fft_np, g.Nphi, st))
+        return fail(PSHT_ERR_NOMEM, "FFT tables");
+    if (p.phi_split && !make_fft_table(p, p.fft_np_half, g.Nphi / 2, st)) return fail(PSHT_ERR_NOMEM, "FFT tables");
+
+    // points: bucket sort into tiles
+    p.ntx = (g.rows_used + p.tile_x - 1) / p.tile_x;
+    p.nty = (g.Nphi + p.tile_y - 1) / p.tile_y;
+    p.ntiles = p.ntx * p.nty;
+    if (!dalloc(p, p.d_px, (size_t)npoints) || !dalloc(p, p.d_py, (size_t)npoints) ||
+        !dalloc(p, p.d_perm, (size_t)npoints) || !dalloc(p, p.d_tile_start, (size_t)p.ntiles + 1))
+        return fail(PSHT_ERR_NOMEM, "allocating sorted points");
+    {
+        ScopedDevFree keys, cursor;
+        hipError_t e = hipMalloc(&keys.p, sizeof(int32_t) * std::max<int64_t>(npoints, 1));
+        if (e == hipSuccess) e = hipMalloc(&cursor.p, sizeof(int32_t) * (size_t)p.ntiles);
+        if (e != hipSuccess) return device_fail(e, "sort scratch");
+        e = psht::launch_point_sort(p, theta, phi, static_cast<int32_t *>(keys.p), static_cast<int32_t *>(cursor.p), st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(e, "point sort");
+    }
+
+    // workspace per map
+    const size_t cs = fp32 ? 8 : 16;
+    p.ws_F = align256((size_t)(2 * g.mmax + 1) * g.nring * 16);
+    p.ws_V = align256((size_t)g.rows_used * (2 * g.mmax + 1) * cs);
+    p.ws_U = align256((size_t)g.rows_used * g.Nphi * cs);
+    p.ws_per_map = p.ws_F + p.ws_V + p.ws_U;
+    *out = plan.release();
+    return PSHT_OK;
+}
+
+bool check_ws(const psht_plan_s &p, int nmaps, void *ws, size_t ws_bytes) {
+    if (nmaps == 0) return true;
+    return ws != nullptr && ws_bytes >= (size_t)nmaps * p.ws_per_map;
+}
+
+}  // namespace
+
+extern "C" {
+
+psht_status psht_plan_create(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
+                             const double *phi, double epsilon, int precision, void *hip_stream) {
+    try {
+        return plan_create_impl(out, lmax, spin, npoints, theta, phi, epsilon, precision,
+                                static_cast<hipStream_t>(hip_stream));
+    } catch (const std::bad_alloc &) {
+        return fail(PSHT_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(PSHT_ERR_DEVICE, e.what());
+    } catch (...) {
+        return fail(PSHT_ERR_DEVICE, "unknown error");
+    }
+}
+
+psht_status psht_plan_query(psht_plan plan, psht_plan_info *info) {
+    if (!plan || !info) return fail(PSHT_ERR_ARG, "plan or info is NULL");
+    fill_info(*plan, info);
+    return PSHT_OK;
+}
+
+psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
+                       void *hip_stream) {
+    if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
+    if (nmaps < 0) return fail(PSHT_ERR_ARG, "nmaps < 0");
+    if (nmaps > 0 && (!alm || (!map && plan->npts > 0))) return fail(PSHT_ERR_ARG, "alm or map is NULL");
+    if (!check_ws(*plan, nmaps, workspace, ws_bytes))
+        return fail(PSHT_ERR_WORKSPACE, "workspace smaller than nmaps * workspace_bytes_per_map");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const psht::Geometry &g = plan->g;
+    const size_t alm_bytes = (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16;
+    const size_t map_bytes = (size_t)plan->npts * (g.fp32 ? 8 : 16);
+    for (int i = 0; i < nmaps; ++i) {
+        char *ws = static_cast<char *>(workspace) + (size_t)i * plan->ws_per_map;
+        double *F = reinterpret_cast<double *>(ws);
+        void *V = ws + plan->ws_F;
+        void *U = ws + plan->ws_F + plan->ws_V;
+        const void *a = static_cast<const char *>(alm) + i * alm_bytes;
+        void *m = static_cast<char *>(map) + i * map_bytes;
+        psht_plan_s &P = *plan;
+        hipError_t e = timed(P, PSHT_T_LEG_SYNTH, st, [&] { return psht::launch_leg_synth(P, a, F, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_THETA_SYNTH, st, [&] { return psht::launch_theta_synth(P, F, V, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_PHI_SYNTH, st, [&] { return psht::launch_phi_synth(P, V, U, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_INTERP, st, [&] { return psht::launch_interp(P, U, m, st); });
+        if (e != hipSuccess) return device_fail(e, "synthesis launch");
+    }
+    return PSHT_OK;
+}
+
+psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm, void *workspace, size_t ws_bytes,
+                         void *hip_stream) {
+    if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
+    if (nmaps < 0) return fail(PSHT_ERR_ARG, "nmaps < 0");
+    if (nmaps > 0 && (!alm || (!map && plan->npts > 0))) return fail(PSHT_ERR_ARG, "alm or map is NULL");
+    if (!check_ws(*plan, nmaps, workspace, ws_bytes))
+        return fail(PSHT_ERR_WORKSPACE, "workspace smaller than nmaps * workspace_bytes_per_map");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const psht::Geometry &g = plan->g;
+    const size_t alm_bytes = (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16;
+    const size_t map_bytes = (size_t)plan->npts * (g.fp32 ? 8 : 16);
+    for (int i = 0; i < nmaps; ++i) {
+        char *ws = static_cast<char *>(workspace) + (size_t)i * plan->ws_per_map;
+        double *F = reinterpret_cast<double *>(ws);
+        void *V = ws + plan->ws_F;
+        void *U = ws + plan->ws_F + plan->ws_V;
+        void *a = static_cast<char *>(alm) + i * alm_bytes;
+        const void *m = static_cast<const char *>(map) + i * map_bytes;
+        psht_plan_s &P = *plan;
+        hipError_t e = timed(P, PSHT_T_GRID_ZERO, st, [&] { return psht::launch_fill_zero(U, P.ws_U, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_SPREAD, st, [&] { return psht::launch_spread(P, m, U, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_PHI_ADJ, st, [&] { return psht::launch_phi_adjoint(P, U, V, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_THETA_ADJ, st, [&] { return psht::launch_theta_adjoint(P, V, F, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_ALM_ZERO, st, [&] { return psht::launch_fill_zero(a, alm_bytes, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_LEG_ADJ, st, [&] { return psht::launch_leg_adjoint(P, F, a, st); });
+        if (e != hipSuccess) return device_fail(e, "adjoint launch");
+    }
+    return PSHT_OK;
+}
+
+void psht_plan_destroy(psht_plan plan) { free_plan(plan); }
+
+psht_status psht_plan_set_timing(psht_plan plan, int enable) {
+    if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
+    for (auto &e : plan->pending) {
+        (void)hipEventSynchronize(e.second.second);
+        plan->event_pool.push_back(e.second.first);
+        plan->event_pool.push_back(e.second.second);
+    }
+    plan->pending.clear();
+    for (int i = 0; i < PSHT_T_COUNT; ++i) {
+        plan->t_ms[i] = 0;
+        plan->t_launches[i] = 0;
+    }
+    plan->timing = enable != 0;
+    return PSHT_OK;
+}
+
+psht_status psht_plan_timing(psht_plan plan, double *ms, int64_t *launches) {
+    if (!plan || !ms || !launches) return fail(PSHT_ERR_ARG, "NULL argument");
+    for (auto &e : plan->pending) {
+        hipError_t r = hipEventSynchronize(e.second.second);
+        float t = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&t, e.second.first, e.second.second);
+        if (r != hipSuccess) return device_fail(r, "timing events");
+        plan->t_ms[e.first] += t;
+        plan->t_launches[e.first] += 1;
+        plan->event_pool.push_back(e.second.first);
+        plan->event_pool.push_back(e.second.second);
+    }
+    plan->pending.clear();
+    for (int i = 0; i < PSHT_T_COUNT; ++i) {
+        ms[i] = plan->t_ms[i];
+        launches[i] = plan->t_launches[i];
+    }
+    return PSHT_OK;
+}
+
+const char *psht_last_error(void) { return g_last_error.c_str(); }
+
+psht_status psht_plan_geometry(int lmax, int spin, double theta_star, double epsilon, int precision,
+                               psht_plan_info *info, double *ring_theta, double *ring_weight, int32_t *ring_mmax,
+                               int capacity) {
+    try {
+        if (!info) return fail(PSHT_ERR_ARG, "info is NULL");
+        if (capacity < 0 || (capacity > 0 && (!ring_theta || !ring_weight || !ring_mmax)))
+            return fail(PSHT_ERR_ARG, "ring arrays are NULL");
+        psht_plan_s p;
+        psht::Error err;
+        if (!psht::geometry_compute(p.g, lmax, spin, theta_star, 0.0, epsilon, precision, false, err, capacity > 0))
+            return fail(err);
+        fill_info(p, info);
+        info->workspace_bytes_per_map = 0;
+        info->resident_bytes = 0;
+        int n = std::min(capacity, p.g.nring);
+        for (int j = 0; j < n; ++j) {
+            ring_theta[j] = p.g.ring_theta[j];
+            ring_weight[j] = p.g.ring_w[j];
+            ring_mmax[j] = p.g.ring_mmax[j];
+        }
+        return PSHT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(PSHT_ERR_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(PSHT_ERR_DEVICE, "unknown error");
+    }
+}
+
+psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, void *hip_stream) {
+    if (!plan || !in || !out) return fail(PSHT_ERR_ARG, "plan, in or out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const psht::Geometry &g = plan->g;
+    hipError_t e;
+    if (stage == PSHT_STAGE_LEGENDRE_SYNTH) {
+        e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
+        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), st);
+    } else if (stage == PSHT_STAGE_LEGENDRE_ADJOINT) {
+        e = psht::launch_fill_zero(out, (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16, st);
+        if (e == hipSuccess) e = psht::launch_leg_adjoint(*plan, static_cast<const double *>(in), out, st);
+    } else {
+        return fail(PSHT_ERR_ARG, "unknown stage");
+    }
+    if (e != hipSuccess) return device_fail(e, "stage launch");
+    return PSHT_OK;
+}
+
+psht_status psht_fft(int n, int batch, int sign, int fp32, const void *in, void *out, void *hip_stream) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, psht_plan_s *> tables;  // kept for the process lifetime
+    if (n < 1 || batch < 0 || (sign != 1 && sign != -1)) return fail(PSHT_ERR_ARG, "bad n, batch or sign");
+    if (batch > 0 && (!in || !out)) return fail(PSHT_ERR_ARG, "in or out is NULL");
+    if (n > (fp32 ? psht::kFftMaxLds32 : psht::kFftMaxLds64)) return fail(PSHT_ERR_UNSUPPORTED, "n above the LDS limit");
+    psht::FftFactors f;
+    if (!psht::fft_factor(n, f)) return fail(PSHT_ERR_UNSUPPORTED, "n has a prime factor outside 2,3,5,7,11,13");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    psht_plan_s *holder;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        auto key = std::make_pair(n, dev);
+        auto it = tables.find(key);
+        if (it == tables.end()) {
+            holder = new psht_plan_s();
+            if (!make_fft_table(*holder, holder->fft_np, n, st) || hipStreamSynchronize(st) != hipSuccess) {
+                free_plan(holder);
+                return fail(PSHT_ERR_NOMEM, "FFT table");
+            }
+            tables[key] = holder;
+        } else {
+            holder = it->second;
+        }
+    }
+    hipError_t e = psht::launch_fft_rows(holder->fft_np, batch, sign, fp32 != 0, in, out, st);
+    if (e != hipSuccess) return device_fail(e, "fft launch");
+    return PSHT_OK;
+}
+
+// Host evaluation of lambda+-_lm(theta), l = 0..lmax, with the tables, seeds,
+// recurrence and rescaling the GPU kernels use (values still scaled below the
+// double range are reported as zero).
+psht_status psht_legendre_column(int lmax, int spin, int m, double theta, double *lam_plus, double *lam_minus) {
+    if (lmax < 0 || spin < 0 || spin > lmax || m < 0 || m > lmax || !lam_plus || !lam_minus)
+        return fail(PSHT_ERR_ARG, "bad arguments");
+    try {
+        psht::LegTable t;
+        psht::leg_table_host(t, lmax, spin);
+        for (int l = 0; l <= lmax; ++l) lam_plus[l] = lam_minus[l] = 0.0;
+        const int l0 = std::max(m, spin);
+        double up, um, upp = 0.0, ump = 0.0;
+        int kp, km;
+        psht::leg_seed(t.h_kmant[m], t.h_kexp[m], m, spin, std::cos(theta / 2), std::sin(theta / 2), up, kp, um, km);
+        const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+        const double sh = std::sin(theta / 2), y = 2 * sh * sh;
+        for (int l = l0; l <= lmax; ++l) {
+            const double *c = &t.h_coef[4 * (base + l)];
+            lam_plus[l] = kp == 0 ? c[3] * up : 0.0;
+            lam_minus[l] = km == 0 ? c[3] * um : 0.0;
+            if (l < lmax) {
+                double np = std::fma(std::fma(c[0], y, c[1]), up, -upp);
+                upp = up;
+                up = np;
+                psht::leg_rescale(up, upp, kp);
+                double nm = std::fma(std::fma(c[0], y, c[2]), um, -ump);
+                ump = um;
+                um = nm;
+                psht::leg_rescale(um, ump, km);
+            }
+        }
+        return PSHT_OK;
+    } catch (...) {
+        return fail(PSHT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,403 @@
+// Non-uniform stage of the Fourier-sphere route on gfx950: type-2
+// interpolation (synthesis) and type-1 spreading (adjoint) with the
+// exponential-of-semicircle kernel psi(z) = exp(beta (sqrt(1 - z^2) - 1)),
+// plus the plan-time point statistics and the bucket sort of the points into
+// grid tiles.
+//
+// Grid: rows a = row_lo .. row_lo + rows_used - 1 of the oversampled Theta grid
+// (spacing 2 pi / Ntheta, Theta = theta pi / theta_max, Sec. II step 3) and all
+// Nphi columns (spacing 2 pi / Nphi).  A point with grid coordinates
+// (X, Y) = (theta sx, phi sy) touches rows a0 .. a0 + W - 1, a0 = ceil(X - W/2),
+// and columns b0 .. b0 + W - 1 (mod Nphi), b0 = ceil(Y - W/2).
+//
+// Tiles: the points are bucket-sorted by the tile of (a0, b0); a tile covers
+// tile_x x tile_y stencil origins, so its points touch a (tile_x + W - 1) x
+// (tile_y + W - 1) subgrid.  One workgroup per tile stages that subgrid in
+// LDS: interpolation reads it once from HBM; spreading accumulates into it
+// with LDS atomics and flushes it with one global atomic per cell.
+#include "psht_internal.h"
+
+namespace psht {
+
+constexpr int kTileThreads = 256;
+
+struct NufftArgs {
+    int W;
+    double beta;
+    int rows_used, Nphi, tile_x, tile_y, ntx, nty;
+    int row_lo;
+    const double *px, *py;
+    const int32_t *perm;
+    const int32_t *tile_start;
+};
+
+__device__ __host__ inline int stencil_origin(double X, int W) { return (int)ceil(X - 0.5 * W); }
+
+__device__ inline double es_kernel(double z, double beta) {
+    double t = fmax(0.0, 1.0 - z * z);
+    return exp(beta * (sqrt(t) - 1.0));
+}
+
+template <int W>
+__device__ inline void es_weights(double X, int a0, double beta, double *k) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) k[i] = es_kernel((X - (double)(a0 + i)) * (2.0 / W), beta);
+}
+
+template <typename T> struct CplxT;
+template <> struct CplxT<double> { typedef double2 type; };
+template <> struct CplxT<float> { typedef float2 type; };
+
+// Tile index -> (tx, ty); tiles with no points return immediately.
+template <typename T, int W>
+__global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const typename CplxT<T>::type *U,
+                                                         typename CplxT<T>::type *map) {
+    typedef typename CplxT<T>::type C;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *S = reinterpret_cast<C *>(smem);
+    const int t = blockIdx.x;
+    const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
+    if (p0 == p1) return;
+    const int tx = t / a.nty, ty = t - tx * a.nty;
+    const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1;
+    const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
+    for (int e = threadIdx.x; e < SX * SY; e += kTileThreads) {
+        const int i = e / SY, j = e - i * SY;
+        const int row = r0 + i;
+        const int col = (c0 + j) % a.Nphi;  // the subgrid may wrap more than once when Nphi is small
+        C v;
+        v.x = v.y = (T)0;
+        if (row < a.rows_used) v = U[(int64_t)row * a.Nphi + col];
+        S[e] = v;
+    }
+    __syncthreads();
+    for (int p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
+        const double X = a.px[p], Y = a.py[p];
+        const int a0 = stencil_origin(X, W), b0 = stencil_origin(Y, W);
+        int b0m = b0 % a.Nphi;
+        if (b0m < 0) b0m += a.Nphi;
+        const int li = a0 - a.row_lo - r0, lj = b0m - c0;
+        // By construction of the sort 0 <= li < tile_x and 0 <= lj < tile_y; the
+        // guard only keeps LDS accesses in bounds.
+        if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
+        double kx[W], ky[W];
+        es_weights<W>(X, a0, a.beta, kx);
+        es_weights<W>(Y, b0, a.beta, ky);
+        double accr = 0.0, acci = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const C *Srow = S + (li + i) * SY + lj;
+            double rr = 0.0, ri = 0.0;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                C v = Srow[j];
+                rr = fma(ky[j], (double)v.x, rr);
+                ri = fma(ky[j], (double)v.y, ri);
+            }
+            accr = fma(kx[i], rr, accr);
+            acci = fma(kx[i], ri, acci);
+        }
+        C out;
+        out.x = (T)accr;
+        out.y = (T)acci;
+        map[a.perm[p]] = out;
+    }
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const typename CplxT<T>::type *map,
+                                                         T *U) {
+    typedef typename CplxT<T>::type C;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *S = reinterpret_cast<T *>(smem);  // interleaved (re, im)
+    const int t = blockIdx.x;
+    const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
+    if (p0 == p1) return;
+    const int tx = t / a.nty, ty = t - tx * a.nty;
+    const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1;
+    const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
+    for (int e = threadIdx.x; e < 2 * SX * SY; e += kTileThreads) S[e] = (T)0;
+    __syncthreads();
+    for (int p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
+        const double X = a.px[p], Y = a.py[p];
+        const int a0 = stencil_origin(X, W), b0 = stencil_origin(Y, W);
+        int b0m = b0 % a.Nphi;
+        if (b0m < 0) b0m += a.Nphi;
+        const int li = a0 - a.row_lo - r0, lj = b0m - c0;
+        if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
+        double kx[W], ky[W];
+        es_weights<W>(X, a0, a.beta, kx);
+        es_weights<W>(Y, b0, a.beta, ky);
+        const C f = map[a.perm[p]];
+        const double fr = f.x, fi = f.y;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            T *Srow = S + 2 * ((li + i) * SY + lj);
+            const double wr = kx[i] * fr, wi = kx[i] * fi;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                atomicAdd(Srow + 2 * j, (T)(wr * ky[j]));
+                atomicAdd(Srow + 2 * j + 1, (T)(wi * ky[j]));
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < SX * SY; e += kTileThreads) {
+        const int i = e / SY, j = e - i * SY;
+        const int row = r0 + i;
+        if (row >= a.rows_used) continue;
+        const T vr = S[2 * e], vi = S[2 * e + 1];
+        if (vr == (T)0 && vi == (T)0) continue;
+        const int col = (c0 + j) % a.Nphi;  // the subgrid may wrap more than once when Nphi is small
+        T *dst = U + 2 * ((int64_t)row * a.Nphi + col);
+        atomicAdd(dst, vr);
+        atomicAdd(dst + 1, vi);
+    }
+}
+
+static NufftArgs nufft_args(const psht_plan_s &p) {
+    NufftArgs a;
+    a.W = p.g.W;
+    a.beta = p.g.beta;
+    a.rows_used = p.g.rows_used;
+    a.Nphi = p.g.Nphi;
+    a.tile_x = p.tile_x;
+    a.tile_y = p.tile_y;
+    a.ntx = p.ntx;
+    a.nty = p.nty;
+    a.row_lo = p.g.row_lo;
+    a.px = p.d_px;
+    a.py = p.d_py;
+    a.perm = p.d_perm;
+    a.tile_start = p.d_tile_start;
+    return a;
+}
+
+template <typename T, int W>
+static hipError_t launch_interp_w(const psht_plan_s &p, const void *U, void *map, hipStream_t st) {
+    typedef typename CplxT<T>::type C;
+    NufftArgs a = nufft_args(p);
+    size_t lds = (size_t)(p.tile_x + W - 1) * (p.tile_y + W - 1) * sizeof(C);
+    hipLaunchKernelGGL((k_interp<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
+                       static_cast<const C *>(U), static_cast<C *>(map));
+    return hipGetLastError();
+}
+
+template <typename T, int W>
+static hipError_t launch_spread_w(const psht_plan_s &p, const void *map, void *U, hipStream_t st) {
+    typedef typename CplxT<T>::type C;
+    NufftArgs a = nufft_args(p);
+    size_t lds = (size_t)(p.tile_x + W - 1) * (p.tile_y + W - 1) * sizeof(C);
+    hipLaunchKernelGGL((k_spread<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
+                       static_cast<const C *>(map), static_cast<T *>(U));
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t dispatch_interp(const psht_plan_s &p, const void *U, void *map, hipStream_t st) {
+    switch (p.g.W) {
+#define PSHT_W(w) case w: return launch_interp_w<T, w>(p, U, map, st);
+        PSHT_W(2) PSHT_W(3) PSHT_W(4) PSHT_W(5) PSHT_W(6) PSHT_W(7) PSHT_W(8) PSHT_W(9)
+        PSHT_W(10) PSHT_W(11) PSHT_W(12) PSHT_W(13) PSHT_W(14) PSHT_W(15) PSHT_W(16)
+#undef PSHT_W
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t dispatch_spread(const psht_plan_s &p, const void *map, void *U, hipStream_t st) {
+    switch (p.g.W) {
+#define PSHT_W(w) case w: return launch_spread_w<T, w>(p, map, U, st);
+        PSHT_W(2) PSHT_W(3) PSHT_W(4) PSHT_W(5) PSHT_W(6) PSHT_W(7) PSHT_W(8) PSHT_W(9)
+        PSHT_W(10) PSHT_W(11) PSHT_W(12) PSHT_W(13) PSHT_W(14) PSHT_W(15) PSHT_W(16)
+#undef PSHT_W
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_interp(const psht_plan_s &p, const void *U, void *map, hipStream_t st) {
+    if (p.npts == 0 || p.ntiles == 0) return hipSuccess;
+    return p.g.fp32 ? dispatch_interp<float>(p, U, map, st) : dispatch_interp<double>(p, U, map, st);
+}
+
+hipError_t launch_spread(const psht_plan_s &p, const void *map, void *U, hipStream_t st) {
+    if (p.npts == 0 || p.ntiles == 0) return hipSuccess;
+    return p.g.fp32 ? dispatch_spread<float>(p, map, U, st) : dispatch_spread<double>(p, map, U, st);
+}
+
+// --------------------------------------------------------------- fill
+
+__global__ void k_fill_zero(uint4 *p, size_t n16) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_fill_zero_bytes(unsigned char *p, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    size_t n16 = bytes / 16;
+    if (n16) {
+        size_t blocks = std::min<size_t>((n16 + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint4 *>(ptr), n16);
+    }
+    size_t rem = bytes - n16 * 16;
+    if (rem)
+        hipLaunchKernelGGL(k_fill_zero_bytes, dim3(1), dim3(256), 0, st, static_cast<unsigned char *>(ptr) + n16 * 16,
+                           rem);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ plan-time points
+
+// Per-block partial statistics: [min theta, max theta, number of invalid points].
+constexpr int kStatBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_point_stats(const double *theta, const double *phi, int64_t n,
+                                                     double *out) {
+    __shared__ double smin[256], smax[256], sbad[256];
+    double mn = 1e300, mx = -1e300, bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double t = theta[i], f = phi[i];
+        const bool ok = (t >= 0.0) && (t <= M_PI) && isfinite(f);
+        if (!ok) bad += 1;
+        else {
+            mn = fmin(mn, t);
+            mx = fmax(mx, t);
+        }
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+            sbad[threadIdx.x] += sbad[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x] = smin[0];
+        out[3 * blockIdx.x + 1] = smax[0];
+        out[3 * blockIdx.x + 2] = sbad[0];
+    }
+}
+
+hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n, double *d_stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_point_stats, dim3(kStatBlocks), dim3(256), 0, st, theta, phi, n, d_stats);
+    return hipGetLastError();
+}
+
+struct SortArgs {
+    double sx, sy;
+    int W, row_lo, rows_used, Nphi, tile_x, tile_y, ntx, nty;
+};
+
+// Grid coordinates of a point; phi is reduced to [0, 2 pi).
+__device__ inline void point_grid(const SortArgs &a, double theta, double phi, double &X, double &Y) {
+    const double twopi = 2.0 * M_PI;
+    double f = phi - twopi * floor(phi / twopi);
+    if (f >= twopi) f -= twopi;
+    if (f < 0.0) f = 0.0;
+    X = theta * a.sx;
+    Y = f * a.sy;
+    if (Y >= (double)a.Nphi) Y -= (double)a.Nphi;
+}
+
+__device__ inline int point_tile(const SortArgs &a, double X, double Y) {
+    const int a0 = stencil_origin(X, a.W), b0 = stencil_origin(Y, a.W);
+    int b0m = b0 % a.Nphi;
+    if (b0m < 0) b0m += a.Nphi;
+    int tx = (a0 - a.row_lo) / a.tile_x;
+    int ty = b0m / a.tile_y;
+    tx = min(max(tx, 0), a.ntx - 1);
+    ty = min(max(ty, 0), a.nty - 1);
+    return tx * a.nty + ty;
+}
+
+__global__ void k_point_keys(SortArgs a, const double *theta, const double *phi, int64_t n, int32_t *keys,
+                             int32_t *count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double X, Y;
+    point_grid(a, theta[i], phi[i], X, Y);
+    int k = point_tile(a, X, Y);
+    keys[i] = k;
+    atomicAdd(&count[k], 1);
+}
+
+// Exclusive scan of count[0..n) into start[0..n] (start[n] = total), one block.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int n, int32_t *start, int32_t *cursor) {
+    __shared__ int32_t part[1024];
+    const int per = (n + 1023) / 1024;
+    const int b = threadIdx.x * per, e = min(n, b + per);
+    int32_t s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+    for (int i = b; i < e; ++i) {
+        const int32_t c = count[i];  // count and cursor may alias
+        start[i] = run;
+        cursor[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) start[n] = part[1023];
+}
+
+__global__ void k_point_scatter(SortArgs a, const double *theta, const double *phi, int64_t n, const int32_t *keys,
+                                int32_t *cursor, double *px, double *py, int32_t *perm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double X, Y;
+    point_grid(a, theta[i], phi[i], X, Y);
+    int pos = atomicAdd(&cursor[keys[i]], 1);
+    px[pos] = X;
+    py[pos] = Y;
+    perm[pos] = (int32_t)i;
+}
+
+hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
+                             int32_t *d_cursor, hipStream_t st) {
+    SortArgs a;
+    a.sx = p.g.sx;
+    a.sy = p.g.sy;
+    a.W = p.g.W;
+    a.row_lo = p.g.row_lo;
+    a.rows_used = p.g.rows_used;
+    a.Nphi = p.g.Nphi;
+    a.tile_x = p.tile_x;
+    a.tile_y = p.tile_y;
+    a.ntx = p.ntx;
+    a.nty = p.nty;
+    const int64_t n = p.npts;
+    hipError_t e = launch_fill_zero(d_cursor, sizeof(int32_t) * (size_t)p.ntiles, st);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        unsigned nb = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_point_keys, dim3(nb), dim3(256), 0, st, a, theta, phi, n, d_keys, d_cursor);
+    }
+    // d_cursor now holds the counts; scan into tile_start and reuse d_cursor as the cursor
+    // (the scan reads each count before it overwrites it within the same thread).
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cursor, p.ntiles, p.d_tile_start, d_cursor);
+    if (n > 0) {
+        unsigned nb = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_point_scatter, dim3(nb), dim3(256), 0, st, a, theta, phi, n, d_keys, d_cursor, p.d_px,
+                           p.d_py, p.d_perm);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace psht

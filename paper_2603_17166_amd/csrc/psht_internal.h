@@ -1,0 +1,161 @@
+// Internal declarations of libpsht: plan geometry (host), device tables and
+// the stage launchers.  Not part of the public interface (include/psht.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/psht.h"
+
+namespace psht {
+
+// Error carried from the internals to the C ABI.
+struct Error {
+    psht_status code = PSHT_OK;
+    std::string msg;
+};
+
+// ---------------------------------------------------------------- geometry
+
+// Everything that follows from (lmax, spin, theta range, epsilon, precision):
+// the parameter rules of Sec. II.B-C, the rings of Sec. II.A, the window of
+// Sec. II.C, the per-ring m cut-offs (polar optimization, Sec. II.A) and the
+// parameters of the exponential-of-semicircle NUFFT.
+struct Geometry {
+    int lmax = 0, spin = 0;
+    double eps = 0;
+    bool fp32 = false;
+    bool full_sky = false;
+    double theta_star = 0, theta_min = 0;
+    double alpha = 0, eps_apo = 0, theta_max = 0;
+    int Lmax = 0, N2 = 0, nring = 0;
+    std::vector<double> ring_theta;   // theta_j (patch colatitude)
+    std::vector<double> ring_w;       // w(Theta_j)
+    std::vector<int32_t> ring_mmax;   // largest m kept on ring j
+    int mmax = 0;
+    // NUFFT
+    int W = 0;
+    double beta = 0, sigma = 2.0;
+    int Ntheta = 0, Nphi = 0;
+    int row_lo = 0, rows_used = 0;
+    double sx = 0, sy = 0;           // grid coordinate = theta*sx (rows), phi*sy (cols)
+    std::vector<double> psihat_theta; // n = 0..Lmax
+    std::vector<double> psihat_phi;   // m = 0..mmax
+    double predicted_speedup = 0;
+    double legendre_triples = 0;
+};
+
+// m cut-off threshold relative to epsilon.
+constexpr double kPolarTauRel = 1e-4;
+
+bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double theta_min,
+                      double eps, int precision, bool with_grid, Error &err, bool with_cutoffs = true);
+
+// Factorization of an FFT length into radices 4, 2, 3, 5, 7, 11, 13.
+struct FftFactors {
+    int n = 0, npass = 0;
+    int radix[24];
+};
+bool fft_factor(int n, FftFactors &f);
+bool is_smooth(int n, const int *primes, int np);
+
+// ------------------------------------------------ Legendre recurrence tables
+
+// Per (m, l): {-A_l, A_l + B_l, A_l - B_l, P_l} of the normalized recurrence
+//   mu_{l+1} = ((A_l +/- B_l) - A_l y) mu_l - mu_{l-1},  y = 1 - cos(theta),
+//   lambda_l = P_l mu_l,
+// for l from l0 = max(m, s) (see leg_common.h), stored at the coefficient
+// index of (l, m).  Seed prefactors K_m = N_l0 sqrt(C(2 l0, m + s)) as
+// (mantissa, exponent).
+struct LegTable {
+    int lmax = 0, spin = 0;
+    double *d_coef = nullptr;   // [nalm][4]
+    double *d_kmant = nullptr;  // [lmax+1]
+    int32_t *d_kexp = nullptr;  // [lmax+1]
+    size_t bytes = 0;
+    std::vector<double> h_coef, h_kmant;
+    std::vector<int32_t> h_kexp;
+    ~LegTable();
+};
+void leg_table_host(LegTable &t, int lmax, int spin);
+std::shared_ptr<LegTable> leg_table_get(int lmax, int spin, Error &err);
+
+struct LegItem {
+    int32_t m, jb, je, pad;  // rings [jb, je) for this m
+};
+
+// ------------------------------------------------------------------- plan
+
+struct FftTable {
+    int n = 0;
+    FftFactors f;
+    double *d_tw = nullptr;  // e^{-2 pi i k / n}, k = 0..n-1, interleaved (re, im)
+};
+
+}  // namespace psht
+
+struct psht_plan_s {
+    psht::Geometry g;
+    int64_t npts = 0;
+    // rings
+    double *d_ring_y = nullptr, *d_ring_ch = nullptr, *d_ring_sh = nullptr, *d_ring_w = nullptr;
+    int32_t *d_ring_mmax = nullptr;
+    // Legendre work lists: synthesis (blocks of ring chunks per m)
+    psht::LegItem *d_leg_items = nullptr;
+    int n_leg_items = 0;
+    int leg_rings_per_item = 0;
+    std::shared_ptr<psht::LegTable> leg;
+    // NUFFT tables
+    double *d_psihat_t = nullptr, *d_psihat_p = nullptr;
+    psht::FftTable fft_n2, fft_nt, fft_np, fft_np_half;
+    bool phi_split = false;
+    // points, sorted by tile
+    int tile_x = 16, tile_y = 32, ntx = 0, nty = 0, ntiles = 0;
+    double *d_px = nullptr, *d_py = nullptr;
+    int32_t *d_perm = nullptr;
+    int32_t *d_tile_start = nullptr;  // ntiles + 1
+    // workspace layout (bytes, per map)
+    size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_per_map = 0;
+    size_t resident = 0;
+    std::vector<void *> allocations;
+    // per-stage HIP-event timing (PSHT_T_* indices)
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> event_pool;
+    double t_ms[PSHT_T_COUNT] = {0};
+    int64_t t_launches[PSHT_T_COUNT] = {0};
+};
+
+namespace psht {
+
+// Stage launchers (defined in the .hip files).  All asynchronous on `st`.
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, hipStream_t st);
+hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, hipStream_t st);
+hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st);
+hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st);
+hipError_t launch_phi_synth(const psht_plan_s &p, const void *V, void *U, hipStream_t st);
+hipError_t launch_phi_adjoint(const psht_plan_s &p, const void *U, void *V, hipStream_t st);
+hipError_t launch_interp(const psht_plan_s &p, const void *U, void *map, hipStream_t st);
+hipError_t launch_spread(const psht_plan_s &p, const void *map, void *U, hipStream_t st);
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
+hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, const void *in, void *out,
+                           hipStream_t st);
+
+// Plan-time point kernels.
+hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n, double *d_stats,
+                              hipStream_t st);
+hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
+                             int32_t *d_cursor, hipStream_t st);
+
+// Rings handled by one Legendre work item (64 lanes x rings per lane).
+int leg_rings_per_item();
+
+// Largest FFT length one workgroup transforms in LDS.
+constexpr int kFftMaxLds64 = 8192;
+constexpr int kFftMaxLds32 = 8192;
+
+}  // namespace psht

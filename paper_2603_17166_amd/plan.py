@@ -1,0 +1,208 @@
+"""Python binding of the partial-sky SHT: plans, synthesis and adjoint.
+
+Thin marshalling over the C ABI (include/psht.h): torch provides device
+memory and the current HIP stream; every step of the transform runs in the
+library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def nalm(lmax: int) -> int:
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _device_f64(x, device) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=device)
+    return t.contiguous()
+
+
+class Plan:
+    """Plan for spin-`spin` synthesis / adjoint at the points (theta, phi)
+    (patch frame: patch centre at the north pole), band limit `lmax`, target
+    accuracy `epsilon`; precision "auto" (FP32 grid when epsilon >= 1e-6),
+    "fp32" or "fp64"."""
+
+    def __init__(self, theta, phi, lmax: int, spin: int, epsilon: float, precision: str = "auto", device=None,
+                 stream=None):
+        lib = _lib.load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        th = _device_f64(theta, self.device)
+        ph = _device_f64(phi, self.device)
+        if th.shape != ph.shape or th.dim() != 1:
+            raise ValueError("theta and phi must be 1-D arrays of equal length")
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _stream(stream)
+            _lib.check(lib.psht_plan_create(ctypes.byref(handle), int(lmax), int(spin), int(th.shape[0]),
+                                            th.data_ptr() or None, ph.data_ptr() or None, float(epsilon),
+                                            _lib.PREC[precision], st))
+        self._h = handle
+        info = _lib.PlanInfo()
+        _lib.check(lib.psht_plan_query(self._h, ctypes.byref(info)))
+        self.info = info.as_dict()
+        self.lmax, self.spin, self.npoints = int(lmax), int(spin), int(th.shape[0])
+        self.map_dtype = torch.complex64 if info.map_is_fp32 else torch.complex128
+        self._ws = None
+
+    # -- resources ---------------------------------------------------------
+    def workspace(self, nmaps: int = 1) -> torch.Tensor:
+        need = max(1, nmaps * self.info["workspace_bytes_per_map"])
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            _lib.load().psht_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- transforms --------------------------------------------------------
+    def _alm_in(self, alm: torch.Tensor):
+        if alm.dtype != torch.complex128:
+            raise TypeError("alm must be complex128")
+        if alm.device != self.device:
+            raise ValueError("alm is on %s, plan on %s" % (alm.device, self.device))
+        single = alm.dim() == 2
+        a = alm.unsqueeze(0) if single else alm
+        if a.dim() != 3 or a.shape[1:] != (2, nalm(self.lmax)):
+            raise ValueError("alm must have shape (2, nalm) or (nmaps, 2, nalm)")
+        return a.contiguous(), single
+
+    def synth(self, alm: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Synthesis general (eq. syn): alm (2, nalm) or (nmaps, 2, nalm) complex128 -> map."""
+        a, single = self._alm_in(alm)
+        nm = a.shape[0]
+        if out is None:
+            out = torch.empty((nm, self.npoints), dtype=self.map_dtype, device=self.device)
+        else:
+            out = out.view(nm, self.npoints)
+            if out.dtype != self.map_dtype or not out.is_contiguous():
+                raise ValueError("out must be a contiguous %s tensor" % self.map_dtype)
+        ws = self.workspace(nm)
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().psht_synth(self._h, nm, a.data_ptr(), out.data_ptr() or None, ws.data_ptr(),
+                                              ws.numel(), _stream(stream)))
+        return out[0] if single else out
+
+    def adjoint(self, fmap: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Adjoint synthesis general: map (npts,) or (nmaps, npts) -> alm (.., 2, nalm) complex128."""
+        if fmap.dtype != self.map_dtype:
+            raise TypeError("map must be %s for this plan" % self.map_dtype)
+        if fmap.device != self.device:
+            raise ValueError("map is on %s, plan on %s" % (fmap.device, self.device))
+        single = fmap.dim() == 1
+        f = (fmap.unsqueeze(0) if single else fmap).contiguous()
+        if f.shape[1] != self.npoints:
+            raise ValueError("map has %d points, plan %d" % (f.shape[1], self.npoints))
+        nm = f.shape[0]
+        if out is None:
+            out = torch.empty((nm, 2, nalm(self.lmax)), dtype=torch.complex128, device=self.device)
+        ws = self.workspace(nm)
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().psht_adjoint(self._h, nm, f.data_ptr() or None, out.data_ptr(), ws.data_ptr(),
+                                                ws.numel(), _stream(stream)))
+        return out[0] if single else out
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Record HIP events around every stage launch of later calls (and reset the totals)."""
+        _lib.check(_lib.load().psht_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """{stage: (total ms, launches)} since timing was enabled (synchronises the events)."""
+        ms = (ctypes.c_double * 10)()
+        n = (ctypes.c_int64 * 10)()
+        _lib.check(_lib.load().psht_plan_timing(self._h, ms, n))
+        return {name: (ms[i], n[i]) for i, name in enumerate(_lib.STAGE_NAMES)}
+
+    def stage(self, stage: int, inp: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().psht_stage(self._h, stage, inp.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def legendre_synth(self, alm: torch.Tensor) -> torch.Tensor:
+        """Per-ring Fourier coefficients F_m(theta_j), shape (2 mmax + 1, Lmax + 1)."""
+        out = torch.empty((2 * self.info["mmax"] + 1, self.info["Lmax"] + 1), dtype=torch.complex128,
+                          device=self.device)
+        return self.stage(_lib.STAGE_LEGENDRE_SYNTH, alm.contiguous(), out)
+
+    def legendre_adjoint(self, F: torch.Tensor) -> torch.Tensor:
+        out = torch.empty((2, nalm(self.lmax)), dtype=torch.complex128, device=self.device)
+        return self.stage(_lib.STAGE_LEGENDRE_ADJOINT, F.contiguous(), out)
+
+
+def synth(alm, theta, phi, lmax, spin, epsilon, precision="auto"):
+    """One-shot synthesis (builds and drops a plan)."""
+    p = Plan(theta, phi, lmax, spin, epsilon, precision)
+    try:
+        return p.synth(alm)
+    finally:
+        p.close()
+
+
+def adjoint(fmap, theta, phi, lmax, spin, epsilon, precision="auto"):
+    """One-shot adjoint synthesis (builds and drops a plan)."""
+    p = Plan(theta, phi, lmax, spin, epsilon, precision)
+    try:
+        return p.adjoint(fmap)
+    finally:
+        p.close()
+
+
+def plan_geometry(lmax: int, spin: int, theta_star: float, epsilon: float, precision: str = "auto"):
+    """Host-only plan parameters for a cap of radius theta_star: (info, ring_theta, ring_w, ring_mmax)."""
+    lib = _lib.load()
+    info = _lib.PlanInfo()
+    _lib.check(lib.psht_plan_geometry(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(info),
+                                      None, None, None, 0))
+    n = info.Lmax + 1
+    th = np.zeros(n)
+    w = np.zeros(n)
+    mm = np.zeros(n, dtype=np.int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.check(lib.psht_plan_geometry(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(info),
+                                      th.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                      mm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n))
+    return info.as_dict(), th, w, mm
+
+
+def legendre_column(lmax: int, spin: int, m: int, theta: float):
+    """lambda+_l and lambda-_l (l = 0..lmax) by the kernels' own seeds/tables, on the host."""
+    lp = np.zeros(lmax + 1)
+    lm = np.zeros(lmax + 1)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.check(_lib.load().psht_legendre_column(lmax, spin, m, theta, lp.ctypes.data_as(dp), lm.ctypes.data_as(dp)))
+    return lp, lm
+
+
+def fft(x: torch.Tensor, sign: int) -> torch.Tensor:
+    """Batched unnormalized FFT along the last axis with the library's LDS FFT kernel."""
+    fp32 = x.dtype == torch.complex64
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    n = x.shape[-1]
+    batch = x.numel() // n if n else 0
+    _lib.check(_lib.load().psht_fft(n, batch, sign, 1 if fp32 else 0, x.data_ptr(), out.data_ptr(),
+                                    _stream()))
+    return out
