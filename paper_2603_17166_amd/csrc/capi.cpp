@@ -256,7 +256,8 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     p.ws_F = align256((size_t)(2 * g.mmax + 1) * g.nring * 16);
     p.ws_V = align256((size_t)g.rows_used * (2 * g.mmax + 1) * cs);
     p.ws_U = align256((size_t)g.rows_used * g.Nphi * cs);
-    p.ws_per_map = p.ws_F + p.ws_V + p.ws_U;
+    p.ws_Q = align256(psht::leg_synth_scratch_bytes(g));
+    p.ws_per_map = p.ws_F + p.ws_V + p.ws_U + p.ws_Q;
     *out = plan.release();
     return PSHT_OK;
 }
@@ -306,10 +307,11 @@ psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, vo
         double *F = reinterpret_cast<double *>(ws);
         void *V = ws + plan->ws_F;
         void *U = ws + plan->ws_F + plan->ws_V;
+        void *Q = ws + plan->ws_F + plan->ws_V + plan->ws_U;
         const void *a = static_cast<const char *>(alm) + i * alm_bytes;
         void *m = static_cast<char *>(map) + i * map_bytes;
         psht_plan_s &P = *plan;
-        hipError_t e = timed(P, PSHT_T_LEG_SYNTH, st, [&] { return psht::launch_leg_synth(P, a, F, st); });
+        hipError_t e = timed(P, PSHT_T_LEG_SYNTH, st, [&] { return psht::launch_leg_synth(P, a, F, Q, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_THETA_SYNTH, st, [&] { return psht::launch_theta_synth(P, F, V, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_PHI_SYNTH, st, [&] { return psht::launch_phi_synth(P, V, U, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_INTERP, st, [&] { return psht::launch_interp(P, U, m, st); });
@@ -422,8 +424,15 @@ psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, voi
     const psht::Geometry &g = plan->g;
     hipError_t e;
     if (stage == PSHT_STAGE_LEGENDRE_SYNTH) {
-        e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
-        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), st);
+        void *scratch = nullptr;
+        e = hipMalloc(&scratch, std::max<size_t>(16, psht::leg_synth_scratch_bytes(g)));
+        if (e == hipSuccess) e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
+        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), scratch, st);
+        if (scratch) {
+            hipError_t e2 = hipStreamSynchronize(st);
+            if (e == hipSuccess) e = e2;
+            (void)hipFree(scratch);
+        }
     } else if (stage == PSHT_STAGE_LEGENDRE_ADJOINT) {
         e = psht::launch_fill_zero(out, (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16, st);
         if (e == hipSuccess) e = psht::launch_leg_adjoint(*plan, static_cast<const double *>(in), out, st);

@@ -14,9 +14,16 @@
 //   g~_lm = -(A + (-1)^s B)/2,  c~_lm = (i/2)(A - (-1)^s B)   (Sec. I, adjoint).
 //
 // Work decomposition: one 64-lane wavefront per (m, chunk of 64*R rings); each
-// lane owns R rings (registers) and runs the recurrence in l; the coefficient
-// table and the alm of order m are wave-uniform and come through the scalar
-// cache.  The work items of one m sit on one XCD so they share its L2.
+// lane owns R rings (registers) and runs the recurrence in l.  The per-(l, m)
+// recurrence coefficients and coefficient combinations are wave-uniform: they
+// come through the scalar cache, loaded one two-l block ahead of their use.
+// The work items of one m run on one XCD so they share its L2.
+//
+// Values below the double range (see leg_common.h) occur only near the start
+// of the l range of the rings where m is close to the cut-off; while any lane
+// of the wave carries one, the wave runs blocks of 8 steps with masked
+// accumulation and renormalises between blocks (8 steps grow a value by far
+// less than the 2^800 of headroom above the renormalisation threshold).
 #include "leg_common.h"
 #include "psht_internal.h"
 
@@ -26,16 +33,16 @@ struct LegArgs {
     const LegItem *items;
     int nitems;
     int group;  // items per order m
-    const double *coef;
+    const double4 *coef;  // {-A, A + B, A - B, P} per (l, m)
     const double *kmant;
     const int32_t *kexp;
     const double *ring_y, *ring_ch, *ring_sh;
     const int32_t *ring_mmax;
     int nring, lmax, spin, mmax;
     int64_t nalm;
-    const double *alm;  // synthesis input, complex [2][nalm]
-    double *alm_out;    // adjoint output, complex [2][nalm]
-    double *F;          // complex [2 mmax + 1][nring]: synthesis output / adjoint input
+    const double4 *Q;  // synthesis: per (l, m) {Re, Im of P(g + i c), Re, Im of P(conj g + i conj c)}
+    double *alm_out;   // adjoint output, complex [2][nalm]
+    double *F;         // complex [2 mmax + 1][nring]: synthesis output / adjoint input
 };
 
 // Block -> item map: the `group` items of one order m run on the same XCD
@@ -47,6 +54,90 @@ __device__ inline int leg_item_index(int bid, int group) {
     return (xcd + 8 * q) * group + i;
 }
 
+// Branch-free renormalisation of a scaled pair (see leg_common.h).
+__device__ inline void rescale_sel(double &cur, double &prev, int &k) {
+    const bool big = (k < 0) && (fabs(cur) > PSHT_RESCALE_HI);
+    const double f = big ? PSHT_RESCALE_FACTOR : 1.0;
+    cur *= f;
+    prev *= f;
+    k += big ? 1 : 0;
+}
+
+// Per-call combination of the coefficients with the normalisation P_l:
+// Q = P {g_r - c_i, g_i + c_r, g_r + c_i, c_r - g_i} (imaginary parts of the
+// m = 0 coefficients dropped), for every (l, m <= mmax).
+__global__ void k_leg_prep(const double2 *g, const double2 *c, const double4 *coef, double4 *Q, int64_t n, int lmax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 a = g[i], b = c[i];
+    if (i <= lmax) {  // m = 0
+        a.y = 0.0;
+        b.y = 0.0;
+    }
+    const double P = coef[i].w;
+    Q[i] = make_double4((a.x - b.y) * P, (a.y + b.x) * P, (a.x + b.y) * P, (b.x - a.y) * P);
+}
+
+template <int R, bool SPIN> struct LegState {
+    double y[R], up[R], upp[R], um[R], ump[R];
+    int kp[R], km[R];
+    bool act[R];
+};
+
+// Seeds of the R rings of this lane for order m.
+template <int R, bool SPIN>
+__device__ inline void leg_init(const LegArgs &a, const LegItem &it, int lane, LegState<R, SPIN> &S) {
+    const int m = it.m, s = a.spin;
+    const double kmant = a.kmant[m];
+    const int kexp = a.kexp[m];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = it.jb + r * 64 + lane;
+        S.act[r] = (j < it.je) && (a.ring_mmax[j] >= m);
+        S.y[r] = 0.0;
+        S.up[r] = S.um[r] = S.upp[r] = S.ump[r] = 0.0;
+        S.kp[r] = S.km[r] = 0;
+        if (S.act[r]) {
+            S.y[r] = a.ring_y[j];
+            leg_seed(kmant, kexp, m, s, a.ring_ch[j], a.ring_sh[j], S.up[r], S.kp[r], S.um[r], S.km[r]);
+            if (!SPIN) {
+                S.um[r] = S.up[r];
+                S.km[r] = S.kp[r];
+            }
+        }
+    }
+}
+
+template <int R, bool SPIN> __device__ inline bool leg_any_scaled(const LegState<R, SPIN> &S) {
+    bool sc = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) sc |= S.act[r] && (S.kp[r] < 0 || (SPIN && S.km[r] < 0));
+    return __any(sc);
+}
+
+// mu_{l+1} = ((A +/- B) - A y) mu_l - mu_{l-1}
+template <int R, bool SPIN> __device__ inline void leg_advance(LegState<R, SPIN> &S, const double4 t) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double np = fma(fma(t.x, S.y[r], t.y), S.up[r], -S.upp[r]);
+        S.upp[r] = S.up[r];
+        S.up[r] = np;
+        if (SPIN) {
+            const double nm = fma(fma(t.x, S.y[r], t.z), S.um[r], -S.ump[r]);
+            S.ump[r] = S.um[r];
+            S.um[r] = nm;
+        }
+    }
+}
+
+template <int R, bool SPIN> __device__ inline void leg_renorm(LegState<R, SPIN> &S) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        rescale_sel(S.up[r], S.upp[r], S.kp[r]);
+        if (SPIN) rescale_sel(S.um[r], S.ump[r], S.km[r]);
+    }
+}
+
 template <int R, bool SPIN>
 __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
     const int idx = leg_item_index(blockIdx.x, a.group);
@@ -54,251 +145,259 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
     const LegItem it = a.items[idx];
     if (it.je <= it.jb) return;
     const int m = it.m, s = a.spin, lane = threadIdx.x;
-    const int l0 = m > s ? m : s;
-    if (l0 > a.lmax) return;
+    const int l0 = m > s ? m : s, lmax = a.lmax;
+    if (l0 > lmax) return;
 
-    double y[R], up[R], upp[R], um[R], ump[R];
+    LegState<R, SPIN> S;
+    leg_init<R, SPIN>(a, it, lane, S);
     double fpr[R], fpi[R], fmr[R], fmi[R];
-    int kp[R], km[R];
-    bool act[R];
-    const double kmant = a.kmant[m];
-    const int kexp = a.kexp[m];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int j = it.jb + r * 64 + lane;
-        act[r] = (j < it.je) && (a.ring_mmax[j] >= m);
-        y[r] = 0.0;
-        up[r] = um[r] = upp[r] = ump[r] = 0.0;
-        kp[r] = km[r] = 0;
-        fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
-        if (act[r]) {
-            y[r] = a.ring_y[j];
-            leg_seed(kmant, kexp, m, s, a.ring_ch[j], a.ring_sh[j], up[r], kp[r], um[r], km[r]);
-            if (!SPIN) { um[r] = up[r]; km[r] = kp[r]; }
-        }
-    }
-    const int64_t base = (int64_t)m * (2 * a.lmax + 1 - m) / 2;
-    const double *T = a.coef + 4 * base;
-    const double2 *G = reinterpret_cast<const double2 *>(a.alm) + base;
-    const double2 *C = reinterpret_cast<const double2 *>(a.alm) + a.nalm + base;
-    const bool m0 = (m == 0);
+    for (int r = 0; r < R; ++r) fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
+
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double4 *T4 = a.coef + base;
+    const double4 *Q4 = a.Q + base;
 
     int l = l0;
-    // Phase 1: some active lane still carries a scaled (negligible) value.
-    bool scaled = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) scaled |= act[r] && (kp[r] < 0 || km[r] < 0);
-    scaled = __any(scaled);
-    while (scaled && l <= a.lmax) {
-        const double P = T[4 * l + 3];
-        double2 g = G[l], c = C[l];
-        if (m0) { g.y = 0.0; c.y = 0.0; }
-        const double apr = (g.x - c.y) * P, api = (g.y + c.x) * P;
-        const double amr = (g.x + c.y) * P, ami = (c.x - g.y) * P;
-        const double nA = T[4 * l], ApB = T[4 * l + 1], AmB = T[4 * l + 2];
-        bool any_scaled = false;
+    bool scaled = leg_any_scaled<R, SPIN>(S);
+    while (scaled && l <= lmax) {
+        double cp[R], cm[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double vp = kp[r] == 0 ? up[r] : 0.0;
-            fpr[r] = fma(apr, vp, fpr[r]);
-            fpi[r] = fma(api, vp, fpi[r]);
-            if (SPIN) {
-                const double vm = km[r] == 0 ? um[r] : 0.0;
-                fmr[r] = fma(amr, vm, fmr[r]);
-                fmi[r] = fma(ami, vm, fmi[r]);
-            } else {
-                fmr[r] = fma(amr, vp, fmr[r]);
-                fmi[r] = fma(ami, vp, fmi[r]);
-            }
-            if (l < a.lmax) {
-                double np = fma(fma(nA, y[r], ApB), up[r], -upp[r]);
-                upp[r] = up[r];
-                up[r] = np;
-                leg_rescale(up[r], upp[r], kp[r]);
-                if (SPIN) {
-                    double nm = fma(fma(nA, y[r], AmB), um[r], -ump[r]);
-                    ump[r] = um[r];
-                    um[r] = nm;
-                    leg_rescale(um[r], ump[r], km[r]);
-                }
-            }
-            any_scaled |= act[r] && (kp[r] < 0 || (SPIN && km[r] < 0));
+            cp[r] = S.kp[r] == 0 ? 1.0 : 0.0;
+            cm[r] = (SPIN ? S.km[r] : S.kp[r]) == 0 ? 1.0 : 0.0;
         }
-        ++l;
-        scaled = __any(any_scaled);
+        const int lend = min(l + 8, lmax + 1);
+        for (; l < lend; ++l) {
+            const double4 q = Q4[l];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double vp = S.up[r] * cp[r], vm = (SPIN ? S.um[r] : S.up[r]) * cm[r];
+                fpr[r] = fma(q.x, vp, fpr[r]);
+                fpi[r] = fma(q.y, vp, fpi[r]);
+                fmr[r] = fma(q.z, vm, fmr[r]);
+                fmi[r] = fma(q.w, vm, fmi[r]);
+            }
+            if (l < lmax) leg_advance<R, SPIN>(S, T4[l]);
+        }
+        leg_renorm<R, SPIN>(S);
+        scaled = leg_any_scaled<R, SPIN>(S);
     }
-    // Phase 2: every active lane is at true scale.
-#pragma unroll 2
-    for (; l <= a.lmax; ++l) {
-        const double P = T[4 * l + 3];
-        double2 g = G[l], c = C[l];
-        if (m0) { g.y = 0.0; c.y = 0.0; }
-        const double apr = (g.x - c.y) * P, api = (g.y + c.x) * P;
-        const double amr = (g.x + c.y) * P, ami = (c.x - g.y) * P;
-        const double nA = T[4 * l], ApB = T[4 * l + 1], AmB = T[4 * l + 2];
+
+    // Main loop: every active lane at true scale; coefficients of the next
+    // two-l block are requested before the current block is computed.
+    if (l + 1 < lmax) {
+        double4 t0 = T4[l], q0 = Q4[l], t1 = T4[l + 1], q1 = Q4[l + 1];
+        // Wait for the first block here, so that the only scalar loads in flight
+        // inside the loop are the next block's (lgkmcnt(0), vmcnt/expcnt untouched).
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        for (;;) {
+            const bool more = l + 3 < lmax;  // next block is a full two-step block
+            double4 t2, q2, t3, q3;
+            if (more) {
+                t2 = T4[l + 2];
+                q2 = Q4[l + 2];
+                t3 = T4[l + 3];
+                q3 = Q4[l + 3];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double vm = SPIN ? S.um[r] : S.up[r];
+                fpr[r] = fma(q0.x, S.up[r], fpr[r]);
+                fpi[r] = fma(q0.y, S.up[r], fpi[r]);
+                fmr[r] = fma(q0.z, vm, fmr[r]);
+                fmi[r] = fma(q0.w, vm, fmi[r]);
+            }
+            leg_advance<R, SPIN>(S, t0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double vm = SPIN ? S.um[r] : S.up[r];
+                fpr[r] = fma(q1.x, S.up[r], fpr[r]);
+                fpi[r] = fma(q1.y, S.up[r], fpi[r]);
+                fmr[r] = fma(q1.z, vm, fmr[r]);
+                fmi[r] = fma(q1.w, vm, fmi[r]);
+            }
+            leg_advance<R, SPIN>(S, t1);
+            l += 2;
+            if (!more) break;
+            t0 = t2;
+            q0 = q2;
+            t1 = t3;
+            q1 = q3;
+        }
+    }
+    for (; l <= lmax; ++l) {
+        const double4 q = Q4[l];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            fpr[r] = fma(apr, up[r], fpr[r]);
-            fpi[r] = fma(api, up[r], fpi[r]);
-            if (SPIN) {
-                fmr[r] = fma(amr, um[r], fmr[r]);
-                fmi[r] = fma(ami, um[r], fmi[r]);
-            } else {
-                fmr[r] = fma(amr, up[r], fmr[r]);
-                fmi[r] = fma(ami, up[r], fmi[r]);
-            }
-            double np = fma(fma(nA, y[r], ApB), up[r], -upp[r]);
-            upp[r] = up[r];
-            up[r] = np;
-            if (SPIN) {
-                double nm = fma(fma(nA, y[r], AmB), um[r], -ump[r]);
-                ump[r] = um[r];
-                um[r] = nm;
-            }
+            const double vm = SPIN ? S.um[r] : S.up[r];
+            fpr[r] = fma(q.x, S.up[r], fpr[r]);
+            fpi[r] = fma(q.y, S.up[r], fpi[r]);
+            fmr[r] = fma(q.z, vm, fmr[r]);
+            fmi[r] = fma(q.w, vm, fmi[r]);
         }
+        if (l < lmax) leg_advance<R, SPIN>(S, T4[l]);
     }
+
     const double sgn_neg = (s & 1) ? 1.0 : -1.0;  // -(-1)^s
     double2 *Fp = reinterpret_cast<double2 *>(a.F) + (int64_t)(a.mmax + m) * a.nring;
     double2 *Fm = reinterpret_cast<double2 *>(a.F) + (int64_t)(a.mmax - m) * a.nring;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (!act[r]) continue;
-        int j = it.jb + r * 64 + lane;
+        if (!S.act[r]) continue;
+        const int j = it.jb + r * 64 + lane;
         Fp[j] = make_double2(-fpr[r], -fpi[r]);
-        if (!m0) Fm[j] = make_double2(sgn_neg * fmr[r], sgn_neg * fmi[r]);
+        if (m != 0) Fm[j] = make_double2(sgn_neg * fmr[r], sgn_neg * fmi[r]);
     }
 }
 
-// Number of l per reduction chunk of the adjoint.
-constexpr int kAdjChunk = 8;
+// ---------------------------------------------------------------- adjoint
+
+constexpr int kAdjChunk = 8;  // l per transposed reduction
+
+// Swap the upper 32 lanes of x with the lower 32 lanes of y (64-bit values).
+__device__ inline void swap32(double &x, double &y) {
+    unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
+    auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    x = __hiloint2double(hi[0], lo[0]);
+    y = __hiloint2double(hi[1], lo[1]);
+}
+
+// Same at 16-lane granularity inside each half of the wave.
+__device__ inline void swap16(double &x, double &y) {
+    unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
+    auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    x = __hiloint2double(hi[0], lo[0]);
+    y = __hiloint2double(hi[1], lo[1]);
+}
 
 template <int R, bool SPIN>
 __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
-    __shared__ double red[kAdjChunk][4][65];
+    __shared__ double red[4][kAdjChunk][17];
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
     if (it.je <= it.jb) return;
     const int m = it.m, s = a.spin, lane = threadIdx.x;
-    const int l0 = m > s ? m : s;
-    if (l0 > a.lmax) return;
+    const int l0 = m > s ? m : s, lmax = a.lmax;
+    if (l0 > lmax) return;
 
-    double y[R], up[R], upp[R], um[R], ump[R];
+    LegState<R, SPIN> S;
+    leg_init<R, SPIN>(a, it, lane, S);
     double fpr[R], fpi[R], fmr[R], fmi[R];
-    int kp[R], km[R];
-    bool act[R];
-    const double kmant = a.kmant[m];
-    const int kexp = a.kexp[m];
     const double2 *Fp = reinterpret_cast<const double2 *>(a.F) + (int64_t)(a.mmax + m) * a.nring;
     const double2 *Fm = reinterpret_cast<const double2 *>(a.F) + (int64_t)(a.mmax - m) * a.nring;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int j = it.jb + r * 64 + lane;
-        act[r] = (j < it.je) && (a.ring_mmax[j] >= m);
-        y[r] = 0.0;
-        up[r] = um[r] = upp[r] = ump[r] = 0.0;
-        kp[r] = km[r] = 0;
         fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
-        if (act[r]) {
-            y[r] = a.ring_y[j];
-            leg_seed(kmant, kexp, m, s, a.ring_ch[j], a.ring_sh[j], up[r], kp[r], um[r], km[r]);
-            if (!SPIN) { um[r] = up[r]; km[r] = kp[r]; }
-            double2 vp = Fp[j], vm = Fm[j];
+        if (S.act[r]) {
+            const int j = it.jb + r * 64 + lane;
+            const double2 vp = Fp[j], vm = Fm[j];
             fpr[r] = vp.x;
             fpi[r] = vp.y;
             fmr[r] = vm.x;
-            fmi[r] = -vm.y;  // conj F'(-m)
+            fmi[r] = -vm.y;  // conj F'(-m); for m = 0 the same column
         }
     }
-    const int64_t base = (int64_t)m * (2 * a.lmax + 1 - m) / 2;
-    const double *T = a.coef + 4 * base;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double4 *T4 = a.coef + base;
     const double sgn_s = (s & 1) ? -1.0 : 1.0;
-    double *out = a.alm_out;
+    const int row = lane >> 4, col = lane & 15;
 
-    bool scaled = false;
+    bool scaled = leg_any_scaled<R, SPIN>(S);
+    for (int lc = l0; lc <= lmax; lc += kAdjChunk) {
+        // per-lane partial sums over the lane's rings, 4 components per l
+        double v[4 * kAdjChunk];
+        double cp[R], cm[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) scaled |= act[r] && (kp[r] < 0 || km[r] < 0);
-    scaled = __any(scaled);
-
-    for (int lc = l0; lc <= a.lmax; lc += kAdjChunk) {
+        for (int r = 0; r < R; ++r) {
+            cp[r] = S.kp[r] == 0 ? 1.0 : 0.0;
+            cm[r] = (SPIN ? S.km[r] : S.kp[r]) == 0 ? 1.0 : 0.0;
+        }
+#pragma unroll
         for (int t = 0; t < kAdjChunk; ++t) {
             const int l = lc + t;
             double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
-            if (l <= a.lmax) {
-                const double nA = T[4 * l], ApB = T[4 * l + 1], AmB = T[4 * l + 2];
-                const bool step = l < a.lmax;
-                bool any_scaled = false;
+            if (l <= lmax) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    double vp = up[r], vm = SPIN ? um[r] : up[r];
+                    double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
                     if (scaled) {
-                        vp = kp[r] == 0 ? vp : 0.0;
-                        vm = (SPIN ? km[r] : kp[r]) == 0 ? vm : 0.0;
+                        vp *= cp[r];
+                        vm *= cm[r];
                     }
                     pa_r = fma(vp, fpr[r], pa_r);
                     pa_i = fma(vp, fpi[r], pa_i);
                     pb_r = fma(vm, fmr[r], pb_r);
                     pb_i = fma(vm, fmi[r], pb_i);
-                    if (step) {
-                        double np = fma(fma(nA, y[r], ApB), up[r], -upp[r]);
-                        upp[r] = up[r];
-                        up[r] = np;
-                        if (SPIN) {
-                            double nm = fma(fma(nA, y[r], AmB), um[r], -ump[r]);
-                            ump[r] = um[r];
-                            um[r] = nm;
-                        }
-                        if (scaled) {
-                            leg_rescale(up[r], upp[r], kp[r]);
-                            if (SPIN) leg_rescale(um[r], ump[r], km[r]);
-                            any_scaled |= act[r] && (kp[r] < 0 || (SPIN && km[r] < 0));
-                        }
-                    }
                 }
-                if (scaled) scaled = __any(any_scaled);
+                if (l < lmax) leg_advance<R, SPIN>(S, T4[l]);
             }
-            red[t][0][lane] = pa_r;
-            red[t][1][lane] = pa_i;
-            red[t][2][lane] = pb_r;
-            red[t][3][lane] = pb_i;
+            v[4 * t + 0] = pa_r;
+            v[4 * t + 1] = pa_i;
+            v[4 * t + 2] = pb_r;
+            v[4 * t + 3] = pb_i;
         }
+        if (scaled) {
+            leg_renorm<R, SPIN>(S);
+            scaled = leg_any_scaled<R, SPIN>(S);
+        }
+        // Transposed reduction over the 64 lanes: two permlane stages leave each
+        // lane with 8 values summed over lanes {i, i^16, i^32, i^48}; value k of
+        // lane i then stands for index k + 8*bit4(i) + 16*bit5(i) of v.
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            swap32(v[k], v[k + 16]);
+            v[k] += v[k + 16];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            swap16(v[k], v[k + 8]);
+            v[k] += v[k + 8];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) red[row][k][col] = v[k];
         __syncthreads();
-        // lane -> (l offset t, component c, half h); each half sums 32 lanes.
-        const int o = lane & 31, h = lane >> 5;
-        const int t = o >> 2, c = o & 3;
+        // output o = (row q, value k) summed over the 16 lanes of row q, two lanes per output
+        const int o = lane & 31, hh = lane >> 5;
+        const int q = o >> 3, k = o & 7;
         double sum = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < 32; ++i) sum += red[t][c][32 * h + i];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) sum += red[q][k][8 * hh + jj];
         sum += __shfl_xor(sum, 32);
-        const double s0 = __shfl(sum, (lane & ~3) | 0);
-        const double s1 = __shfl(sum, (lane & ~3) | 1);
-        const double s2 = __shfl(sum, (lane & ~3) | 2);
-        const double s3 = __shfl(sum, (lane & ~3) | 3);
+        // global index k + 8 (q & 1) + 16 (q >> 1) = 4 t + c: quads of lanes hold the 4 components of one l
+        const int gidx = k + 8 * (q & 1) + 16 * (q >> 1);
+        const int t = gidx >> 2, c = gidx & 3;
+        const int qb = lane & ~3;
+        const double s0 = __shfl(sum, qb | 0), s1 = __shfl(sum, qb | 1), s2 = __shfl(sum, qb | 2),
+                     s3 = __shfl(sum, qb | 3);
         const int l = lc + t;
-        if (h == 0 && l <= a.lmax) {
-            const double P = T[4 * l + 3];
-            double v;
-            int64_t k = base + l;
+        if (hh == 0 && l <= lmax) {
+            const double P = T4[l].w;
+            const int64_t kk = base + l;
+            double val;
             double *dst;
-            if (c == 0) { v = -0.5 * P * (s0 + sgn_s * s2); dst = out + 2 * k; }
-            else if (c == 1) { v = -0.5 * P * (s1 + sgn_s * s3); dst = out + 2 * k + 1; }
-            else if (c == 2) { v = -0.5 * P * (s1 - sgn_s * s3); dst = out + 2 * (a.nalm + k); }
-            else { v = 0.5 * P * (s0 - sgn_s * s2); dst = out + 2 * (a.nalm + k) + 1; }
+            if (c == 0) { val = -0.5 * P * (s0 + sgn_s * s2); dst = a.alm_out + 2 * kk; }
+            else if (c == 1) { val = -0.5 * P * (s1 + sgn_s * s3); dst = a.alm_out + 2 * kk + 1; }
+            else if (c == 2) { val = -0.5 * P * (s1 - sgn_s * s3); dst = a.alm_out + 2 * (a.nalm + kk); }
+            else { val = 0.5 * P * (s0 - sgn_s * s2); dst = a.alm_out + 2 * (a.nalm + kk) + 1; }
             // Im g~_l0 and Im c~_l0 vanish exactly (reality condition).
-            if (!(m == 0 && (c & 1))) atomicAdd(dst, v);
+            if (!(m == 0 && (c & 1))) atomicAdd(dst, val);
         }
         __syncthreads();
     }
 }
 
 template <int R>
-static hipError_t leg_launch(bool adjoint, const psht_plan_s &p, const void *alm, double *F, hipStream_t st) {
+static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out, double *F) {
     const Geometry &g = p.g;
     LegArgs a;
     a.items = p.d_leg_items;
     a.nitems = p.n_leg_items;
     a.group = (g.nring + 64 * R - 1) / (64 * R);
-    a.coef = p.leg->d_coef;
+    a.coef = reinterpret_cast<const double4 *>(p.leg->d_coef);
     a.kmant = p.leg->d_kmant;
     a.kexp = p.leg->d_kexp;
     a.ring_y = p.d_ring_y;
@@ -310,32 +409,46 @@ static hipError_t leg_launch(bool adjoint, const psht_plan_s &p, const void *alm
     a.spin = g.spin;
     a.mmax = g.mmax;
     a.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
-    a.alm = static_cast<const double *>(alm);
-    a.alm_out = static_cast<double *>(const_cast<void *>(alm));
+    a.Q = static_cast<const double4 *>(Q);
+    a.alm_out = static_cast<double *>(const_cast<void *>(alm_out));
     a.F = F;
-    // the item list is padded to a multiple of 8 * group
-    dim3 grid(p.n_leg_items), block(64);
-    if (p.n_leg_items == 0) return hipSuccess;
-    if (!adjoint) {
-        if (g.spin) hipLaunchKernelGGL((k_leg_synth<R, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_leg_synth<R, false>), grid, block, 0, st, a);
-    } else {
-        if (g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_leg_adjoint<R, false>), grid, block, 0, st, a);
-    }
-    return hipGetLastError();
+    return a;
 }
 
 constexpr int kLegR = 4;
 
-hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, hipStream_t st) {
-    return leg_launch<kLegR>(false, p, alm, F, st);
+int leg_rings_per_item() { return 64 * kLegR; }
+
+// Number of (l, m) coefficient entries with m <= mmax.
+static int64_t leg_entries(const Geometry &g) {
+    const int64_t mm = g.mmax;
+    return (mm + 1) * (g.lmax + 1) - mm * (mm + 1) / 2;
+}
+
+size_t leg_synth_scratch_bytes(const Geometry &g) { return (size_t)leg_entries(g) * sizeof(double4); }
+
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, hipStream_t st) {
+    if (p.n_leg_items == 0) return hipSuccess;
+    const Geometry &g = p.g;
+    const int64_t n = leg_entries(g);
+    const int64_t nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
+    const double2 *gg = static_cast<const double2 *>(alm);
+    hipLaunchKernelGGL(k_leg_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gg, gg + nalm,
+                       reinterpret_cast<const double4 *>(p.leg->d_coef), static_cast<double4 *>(scratch), n, g.lmax);
+    LegArgs a = leg_args<kLegR>(p, scratch, nullptr, F);
+    dim3 grid(p.n_leg_items), block(64);
+    if (g.spin) hipLaunchKernelGGL((k_leg_synth<kLegR, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_leg_synth<kLegR, false>), grid, block, 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, hipStream_t st) {
-    return leg_launch<kLegR>(true, p, alm, const_cast<double *>(F), st);
+    if (p.n_leg_items == 0) return hipSuccess;
+    LegArgs a = leg_args<kLegR>(p, nullptr, alm, const_cast<double *>(F));
+    dim3 grid(p.n_leg_items), block(64);
+    if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<kLegR, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_leg_adjoint<kLegR, false>), grid, block, 0, st, a);
+    return hipGetLastError();
 }
-
-int leg_rings_per_item() { return 64 * kLegR; }
 
 }  // namespace psht

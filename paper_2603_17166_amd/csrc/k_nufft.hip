@@ -109,14 +109,16 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
                                                          T *U) {
     typedef typename CplxT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *S = reinterpret_cast<T *>(smem);  // interleaved (re, im)
     const int t = blockIdx.x;
     const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
     if (p0 == p1) return;
     const int tx = t / a.nty, ty = t - tx * a.nty;
     const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1;
+    const int SYP = SY | 1;  // odd row stride spreads neighbouring rows over the LDS banks
+    // separate real and imaginary planes: one 8-byte atomic per lane per instruction
+    T *Sre = reinterpret_cast<T *>(smem), *Sim = Sre + SX * SYP;
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
-    for (int e = threadIdx.x; e < 2 * SX * SY; e += kTileThreads) S[e] = (T)0;
+    for (int e = threadIdx.x; e < 2 * SX * SYP; e += kTileThreads) Sre[e] = (T)0;
     __syncthreads();
     for (int p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
         const double X = a.px[p], Y = a.py[p];
@@ -132,12 +134,12 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         const double fr = f.x, fi = f.y;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            T *Srow = S + 2 * ((li + i) * SY + lj);
+            T *Rre = Sre + (li + i) * SYP + lj, *Rim = Sim + (li + i) * SYP + lj;
             const double wr = kx[i] * fr, wi = kx[i] * fi;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(Srow + 2 * j, (T)(wr * ky[j]));
-                atomicAdd(Srow + 2 * j + 1, (T)(wi * ky[j]));
+                atomicAdd(Rre + j, (T)(wr * ky[j]));
+                atomicAdd(Rim + j, (T)(wi * ky[j]));
             }
         }
     }
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         const int i = e / SY, j = e - i * SY;
         const int row = r0 + i;
         if (row >= a.rows_used) continue;
-        const T vr = S[2 * e], vi = S[2 * e + 1];
+        const T vr = Sre[i * SYP + j], vi = Sim[i * SYP + j];
         if (vr == (T)0 && vi == (T)0) continue;
         const int col = (c0 + j) % a.Nphi;  // the subgrid may wrap more than once when Nphi is small
         T *dst = U + 2 * ((int64_t)row * a.Nphi + col);
@@ -187,7 +189,7 @@ template <typename T, int W>
 static hipError_t launch_spread_w(const psht_plan_s &p, const void *map, void *U, hipStream_t st) {
     typedef typename CplxT<T>::type C;
     NufftArgs a = nufft_args(p);
-    size_t lds = (size_t)(p.tile_x + W - 1) * (p.tile_y + W - 1) * sizeof(C);
+    size_t lds = (size_t)(p.tile_x + W - 1) * ((p.tile_y + W - 1) | 1) * sizeof(C);
     hipLaunchKernelGGL((k_spread<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
                        static_cast<const C *>(map), static_cast<T *>(U));
     return hipGetLastError();

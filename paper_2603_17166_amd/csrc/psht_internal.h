@@ -119,7 +119,7 @@ struct psht_plan_s {
     int32_t *d_perm = nullptr;
     int32_t *d_tile_start = nullptr;  // ntiles + 1
     // workspace layout (bytes, per map)
-    size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_per_map = 0;
+    size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_Q = 0, ws_per_map = 0;
     size_t resident = 0;
     std::vector<void *> allocations;
     // per-stage HIP-event timing (PSHT_T_* indices)
@@ -133,7 +133,9 @@ struct psht_plan_s {
 namespace psht {
 
 // Stage launchers (defined in the .hip files).  All asynchronous on `st`.
-hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, hipStream_t st);
+// Synthesis needs leg_synth_scratch_bytes(g) of scratch (per-call coefficient combinations).
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, hipStream_t st);
+size_t leg_synth_scratch_bytes(const Geometry &g);
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, hipStream_t st);
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st);
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st);
