@@ -199,7 +199,7 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
 
     // Legendre work items: `group` chunks of 64 R rings per order m, groups padded to a multiple of 8.
     {
-        const int chunk = psht::leg_rings_per_item();
+        const int chunk = 64 * psht::leg_rings_per_lane();
         const int group = (g.nring + chunk - 1) / chunk;
         int ngroups = ((g.mmax + 1) + 7) / 8 * 8;
         std::vector<psht::LegItem> items((size_t)ngroups * group, psht::LegItem{0, 0, 0, 0});

@@ -16,14 +16,16 @@
 // Work decomposition: one 64-lane wavefront per (m, chunk of 64*R rings); each
 // lane owns R rings (registers) and runs the recurrence in l.  The per-(l, m)
 // recurrence coefficients and coefficient combinations are wave-uniform: they
-// come through the scalar cache, loaded one two-l block ahead of their use.
-// The work items of one m run on one XCD so they share its L2.
+// are staged through LDS one chunk ahead of their use.  The work items of one
+// m run on one XCD so they share its L2.
 //
 // Values below the double range (see leg_common.h) occur only near the start
 // of the l range of the rings where m is close to the cut-off; while any lane
 // of the wave carries one, the wave runs blocks of 8 steps with masked
 // accumulation and renormalises between blocks (8 steps grow a value by far
 // less than the 2^800 of headroom above the renormalisation threshold).
+#include <cstdlib>
+
 #include "leg_common.h"
 #include "psht_internal.h"
 
@@ -138,8 +140,63 @@ template <int R, bool SPIN> __device__ inline void leg_renorm(LegState<R, SPIN> 
     }
 }
 
+// The coefficient stream of one order m ({-A, A+B, A-B, P} and, for the
+// synthesis, the combinations Q) is staged through LDS in chunks of kStage
+// steps: every lane loads one 32-byte entry of the next chunk (coalesced)
+// while the current chunk is computed from wave-uniform (broadcast) LDS reads.
+constexpr int kStage = 32;
+
+// Entry `lane` of the chunk starting at c: lanes 0..31 read the recurrence
+// table, lanes 32..63 the second stream (when there is one).
+__device__ inline double4 stage_entry(const double4 *T4, const double4 *Q4, int c, int lmax, int lane) {
+    const int l = c + (lane & 31);
+    double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (l <= lmax) {
+        if (lane < 32) v = T4[l];
+        else if (Q4) v = Q4[l];
+    }
+    return v;
+}
+
+// Steps t in [t0, t1) of a staged chunk starting at l = c (t1 - t0 <= 8):
+// accumulate lambda_l into the ring sums, then advance the recurrence.
+template <int R, bool SPIN, bool MASKED>
+__device__ inline void synth_steps(LegState<R, SPIN> &S, double *fpr, double *fpi, double *fmr, double *fmi,
+                                   const double4 *sT, const double4 *sQ, int t0, int t1, int c, int lmax,
+                                   const double *cp, const double *cm) {
+#pragma unroll 2
+    for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        if (t < t1) {
+            const double4 q = sQ[t];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
+                if (MASKED) {
+                    vp *= cp[r];
+                    vm *= cm[r];
+                }
+                fpr[r] = fma(q.x, vp, fpr[r]);
+                fpi[r] = fma(q.y, vp, fpi[r]);
+                fmr[r] = fma(q.z, vm, fmr[r]);
+                fmi[r] = fma(q.w, vm, fmi[r]);
+            }
+            if (c + t < lmax) leg_advance<R, SPIN>(S, sT[t]);
+        }
+    }
+}
+
+template <int R, bool SPIN> __device__ inline void leg_masks(const LegState<R, SPIN> &S, double *cp, double *cm) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        cp[r] = S.kp[r] == 0 ? 1.0 : 0.0;
+        cm[r] = (SPIN ? S.km[r] : S.kp[r]) == 0 ? 1.0 : 0.0;
+    }
+}
+
 template <int R, bool SPIN>
 __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
+    __shared__ double4 sbuf[2][2][kStage];
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
@@ -148,95 +205,57 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
     const int l0 = m > s ? m : s, lmax = a.lmax;
     if (l0 > lmax) return;
 
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double4 *T4 = a.coef + base;
+    const double4 *Q4 = a.Q + base;
+    sbuf[0][lane >> 5][lane & 31] = stage_entry(T4, Q4, l0, lmax, lane);
+
     LegState<R, SPIN> S;
     leg_init<R, SPIN>(a, it, lane, S);
     double fpr[R], fpi[R], fmr[R], fmi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
-
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double4 *T4 = a.coef + base;
-    const double4 *Q4 = a.Q + base;
-
-    int l = l0;
     bool scaled = leg_any_scaled<R, SPIN>(S);
-    while (scaled && l <= lmax) {
-        double cp[R], cm[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cp[r] = S.kp[r] == 0 ? 1.0 : 0.0;
-            cm[r] = (SPIN ? S.km[r] : S.kp[r]) == 0 ? 1.0 : 0.0;
-        }
-        const int lend = min(l + 8, lmax + 1);
-        for (; l < lend; ++l) {
-            const double4 q = Q4[l];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double vp = S.up[r] * cp[r], vm = (SPIN ? S.um[r] : S.up[r]) * cm[r];
-                fpr[r] = fma(q.x, vp, fpr[r]);
-                fpi[r] = fma(q.y, vp, fpi[r]);
-                fmr[r] = fma(q.z, vm, fmr[r]);
-                fmi[r] = fma(q.w, vm, fmi[r]);
-            }
-            if (l < lmax) leg_advance<R, SPIN>(S, T4[l]);
-        }
-        leg_renorm<R, SPIN>(S);
-        scaled = leg_any_scaled<R, SPIN>(S);
-    }
+    __syncthreads();
 
-    // Main loop: every active lane at true scale; coefficients of the next
-    // two-l block are requested before the current block is computed.
-    if (l + 1 < lmax) {
-        double4 t0 = T4[l], q0 = Q4[l], t1 = T4[l + 1], q1 = Q4[l + 1];
-        // Wait for the first block here, so that the only scalar loads in flight
-        // inside the loop are the next block's (lgkmcnt(0), vmcnt/expcnt untouched).
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        for (;;) {
-            const bool more = l + 3 < lmax;  // next block is a full two-step block
-            double4 t2, q2, t3, q3;
-            if (more) {
-                t2 = T4[l + 2];
-                q2 = Q4[l + 2];
-                t3 = T4[l + 3];
-                q3 = Q4[l + 3];
-            }
+    int slot = 0;
+    for (int c = l0; c <= lmax; c += kStage) {
+        const bool has_next = c + kStage <= lmax;
+        double4 nv;
+        if (has_next) nv = stage_entry(T4, Q4, c + kStage, lmax, lane);
+        const double4 *sT = sbuf[slot][0], *sQ = sbuf[slot][1];
+        const int n = min(kStage, lmax + 1 - c);
+        if (!scaled && has_next) {
+            // full chunk, every step advances, no lane scaled: no per-step guards
+#pragma unroll 4
+            for (int t = 0; t < kStage; ++t) {
+                const double4 q = sQ[t];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double vm = SPIN ? S.um[r] : S.up[r];
-                fpr[r] = fma(q0.x, S.up[r], fpr[r]);
-                fpi[r] = fma(q0.y, S.up[r], fpi[r]);
-                fmr[r] = fma(q0.z, vm, fmr[r]);
-                fmi[r] = fma(q0.w, vm, fmi[r]);
+                for (int r = 0; r < R; ++r) {
+                    const double vm = SPIN ? S.um[r] : S.up[r];
+                    fpr[r] = fma(q.x, S.up[r], fpr[r]);
+                    fpi[r] = fma(q.y, S.up[r], fpi[r]);
+                    fmr[r] = fma(q.z, vm, fmr[r]);
+                    fmi[r] = fma(q.w, vm, fmi[r]);
+                }
+                leg_advance<R, SPIN>(S, sT[t]);
             }
-            leg_advance<R, SPIN>(S, t0);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double vm = SPIN ? S.um[r] : S.up[r];
-                fpr[r] = fma(q1.x, S.up[r], fpr[r]);
-                fpi[r] = fma(q1.y, S.up[r], fpi[r]);
-                fmr[r] = fma(q1.z, vm, fmr[r]);
-                fmi[r] = fma(q1.w, vm, fmi[r]);
+        } else for (int b = 0; b < n; b += 8) {
+            const int e = min(b + 8, n);
+            if (scaled) {
+                // some lane still below the double range: masked accumulation, then renormalise
+                double cp[R], cm[R];
+                leg_masks<R, SPIN>(S, cp, cm);
+                synth_steps<R, SPIN, true>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lmax, cp, cm);
+                leg_renorm<R, SPIN>(S);
+                scaled = leg_any_scaled<R, SPIN>(S);
+            } else {
+                synth_steps<R, SPIN, false>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lmax, nullptr, nullptr);
             }
-            leg_advance<R, SPIN>(S, t1);
-            l += 2;
-            if (!more) break;
-            t0 = t2;
-            q0 = q2;
-            t1 = t3;
-            q1 = q3;
         }
-    }
-    for (; l <= lmax; ++l) {
-        const double4 q = Q4[l];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double vm = SPIN ? S.um[r] : S.up[r];
-            fpr[r] = fma(q.x, S.up[r], fpr[r]);
-            fpi[r] = fma(q.y, S.up[r], fpi[r]);
-            fmr[r] = fma(q.z, vm, fmr[r]);
-            fmi[r] = fma(q.w, vm, fmi[r]);
-        }
-        if (l < lmax) leg_advance<R, SPIN>(S, T4[l]);
+        if (has_next) sbuf[slot ^ 1][lane >> 5][lane & 31] = nv;
+        __syncthreads();
+        slot ^= 1;
     }
 
     const double sgn_neg = (s & 1) ? 1.0 : -1.0;  // -(-1)^s
@@ -275,6 +294,7 @@ __device__ inline void swap16(double &x, double &y) {
 
 template <int R, bool SPIN>
 __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
+    __shared__ double4 sbuf[2][kStage];
     __shared__ double red[4][kAdjChunk][17];
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
@@ -283,6 +303,10 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     const int m = it.m, s = a.spin, lane = threadIdx.x;
     const int l0 = m > s ? m : s, lmax = a.lmax;
     if (l0 > lmax) return;
+
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double4 *T4 = a.coef + base;
+    if (lane < 32) sbuf[0][lane] = stage_entry(T4, nullptr, l0, lmax, lane);
 
     LegState<R, SPIN> S;
     leg_init<R, SPIN>(a, it, lane, S);
@@ -301,92 +325,118 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
             fmi[r] = -vm.y;  // conj F'(-m); for m = 0 the same column
         }
     }
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double4 *T4 = a.coef + base;
     const double sgn_s = (s & 1) ? -1.0 : 1.0;
     const int row = lane >> 4, col = lane & 15;
-
     bool scaled = leg_any_scaled<R, SPIN>(S);
-    for (int lc = l0; lc <= lmax; lc += kAdjChunk) {
-        // per-lane partial sums over the lane's rings, 4 components per l
-        double v[4 * kAdjChunk];
-        double cp[R], cm[R];
+    __syncthreads();
+
+    int slot = 0;
+    for (int c = l0; c <= lmax; c += kStage) {
+        const bool has_next = c + kStage <= lmax;
+        double4 nv;
+        if (has_next && lane < 32) nv = stage_entry(T4, nullptr, c + kStage, lmax, lane);
+        const double4 *sT = sbuf[slot];
+        const int n = min(kStage, lmax + 1 - c);
+        for (int b = 0; b < n; b += kAdjChunk) {
+            // per-lane partial sums over the lane's rings, 4 components per l
+            double v[4 * kAdjChunk];
+            double cp[R], cm[R];
+            if (scaled) leg_masks<R, SPIN>(S, cp, cm);
+            const bool plain = !scaled && (c + b + kAdjChunk <= lmax);  // every step advances
+            if (plain) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cp[r] = S.kp[r] == 0 ? 1.0 : 0.0;
-            cm[r] = (SPIN ? S.km[r] : S.kp[r]) == 0 ? 1.0 : 0.0;
-        }
+                for (int u = 0; u < kAdjChunk; ++u) {
+                    double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
 #pragma unroll
-        for (int t = 0; t < kAdjChunk; ++t) {
-            const int l = lc + t;
-            double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
-            if (l <= lmax) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
-                    if (scaled) {
-                        vp *= cp[r];
-                        vm *= cm[r];
+                    for (int r = 0; r < R; ++r) {
+                        const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
+                        pa_r = fma(vp, fpr[r], pa_r);
+                        pa_i = fma(vp, fpi[r], pa_i);
+                        pb_r = fma(vm, fmr[r], pb_r);
+                        pb_i = fma(vm, fmi[r], pb_i);
                     }
-                    pa_r = fma(vp, fpr[r], pa_r);
-                    pa_i = fma(vp, fpi[r], pa_i);
-                    pb_r = fma(vm, fmr[r], pb_r);
-                    pb_i = fma(vm, fmi[r], pb_i);
+                    leg_advance<R, SPIN>(S, sT[b + u]);
+                    v[4 * u + 0] = pa_r;
+                    v[4 * u + 1] = pa_i;
+                    v[4 * u + 2] = pb_r;
+                    v[4 * u + 3] = pb_i;
                 }
-                if (l < lmax) leg_advance<R, SPIN>(S, T4[l]);
+            } else
+#pragma unroll
+            for (int u = 0; u < kAdjChunk; ++u) {
+                const int t = b + u;
+                double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
+                if (t < n) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
+                        if (scaled) {
+                            vp *= cp[r];
+                            vm *= cm[r];
+                        }
+                        pa_r = fma(vp, fpr[r], pa_r);
+                        pa_i = fma(vp, fpi[r], pa_i);
+                        pb_r = fma(vm, fmr[r], pb_r);
+                        pb_i = fma(vm, fmi[r], pb_i);
+                    }
+                    if (c + t < lmax) leg_advance<R, SPIN>(S, sT[t]);
+                }
+                v[4 * u + 0] = pa_r;
+                v[4 * u + 1] = pa_i;
+                v[4 * u + 2] = pb_r;
+                v[4 * u + 3] = pb_i;
             }
-            v[4 * t + 0] = pa_r;
-            v[4 * t + 1] = pa_i;
-            v[4 * t + 2] = pb_r;
-            v[4 * t + 3] = pb_i;
-        }
-        if (scaled) {
-            leg_renorm<R, SPIN>(S);
-            scaled = leg_any_scaled<R, SPIN>(S);
-        }
-        // Transposed reduction over the 64 lanes: two permlane stages leave each
-        // lane with 8 values summed over lanes {i, i^16, i^32, i^48}; value k of
-        // lane i then stands for index k + 8*bit4(i) + 16*bit5(i) of v.
+            if (scaled) {
+                leg_renorm<R, SPIN>(S);
+                scaled = leg_any_scaled<R, SPIN>(S);
+            }
+            // Transposed reduction over the 64 lanes: two permlane stages leave each
+            // lane with 8 values summed over lanes {i, i^16, i^32, i^48}; value k of
+            // lane i then stands for index k + 8*bit4(i) + 16*bit5(i) of v.
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            swap32(v[k], v[k + 16]);
-            v[k] += v[k + 16];
-        }
+            for (int k = 0; k < 16; ++k) {
+                swap32(v[k], v[k + 16]);
+                v[k] += v[k + 16];
+            }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            swap16(v[k], v[k + 8]);
-            v[k] += v[k + 8];
-        }
+            for (int k = 0; k < 8; ++k) {
+                swap16(v[k], v[k + 8]);
+                v[k] += v[k + 8];
+            }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) red[row][k][col] = v[k];
+            for (int k = 0; k < 8; ++k) red[row][k][col] = v[k];
+            __syncthreads();
+            // output o = (row q, value k) summed over the 16 lanes of row q, two lanes per output
+            const int o = lane & 31, hh = lane >> 5;
+            const int q = o >> 3, k = o & 7;
+            double sum = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) sum += red[q][k][8 * hh + jj];
+            sum += __shfl_xor(sum, 32);
+            // global index k + 8 (q & 1) + 16 (q >> 1) = 4 u + c: quads of lanes hold the 4 components of one l
+            const int gidx = k + 8 * (q & 1) + 16 * (q >> 1);
+            const int u = gidx >> 2, cc = gidx & 3;
+            const int qb = lane & ~3;
+            const double s0 = __shfl(sum, qb | 0), s1 = __shfl(sum, qb | 1), s2 = __shfl(sum, qb | 2),
+                         s3 = __shfl(sum, qb | 3);
+            const int t = b + u, l = c + t;
+            if (hh == 0 && t < n) {
+                const double P = sT[t].w;
+                const int64_t kk = base + l;
+                double val;
+                double *dst;
+                if (cc == 0) { val = -0.5 * P * (s0 + sgn_s * s2); dst = a.alm_out + 2 * kk; }
+                else if (cc == 1) { val = -0.5 * P * (s1 + sgn_s * s3); dst = a.alm_out + 2 * kk + 1; }
+                else if (cc == 2) { val = -0.5 * P * (s1 - sgn_s * s3); dst = a.alm_out + 2 * (a.nalm + kk); }
+                else { val = 0.5 * P * (s0 - sgn_s * s2); dst = a.alm_out + 2 * (a.nalm + kk) + 1; }
+                // Im g~_l0 and Im c~_l0 vanish exactly (reality condition).
+                if (!(m == 0 && (cc & 1))) atomicAdd(dst, val);
+            }
+            __syncthreads();
+        }
+        if (has_next && lane < 32) sbuf[slot ^ 1][lane] = nv;
         __syncthreads();
-        // output o = (row q, value k) summed over the 16 lanes of row q, two lanes per output
-        const int o = lane & 31, hh = lane >> 5;
-        const int q = o >> 3, k = o & 7;
-        double sum = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) sum += red[q][k][8 * hh + jj];
-        sum += __shfl_xor(sum, 32);
-        // global index k + 8 (q & 1) + 16 (q >> 1) = 4 t + c: quads of lanes hold the 4 components of one l
-        const int gidx = k + 8 * (q & 1) + 16 * (q >> 1);
-        const int t = gidx >> 2, c = gidx & 3;
-        const int qb = lane & ~3;
-        const double s0 = __shfl(sum, qb | 0), s1 = __shfl(sum, qb | 1), s2 = __shfl(sum, qb | 2),
-                     s3 = __shfl(sum, qb | 3);
-        const int l = lc + t;
-        if (hh == 0 && l <= lmax) {
-            const double P = T4[l].w;
-            const int64_t kk = base + l;
-            double val;
-            double *dst;
-            if (c == 0) { val = -0.5 * P * (s0 + sgn_s * s2); dst = a.alm_out + 2 * kk; }
-            else if (c == 1) { val = -0.5 * P * (s1 + sgn_s * s3); dst = a.alm_out + 2 * kk + 1; }
-            else if (c == 2) { val = -0.5 * P * (s1 - sgn_s * s3); dst = a.alm_out + 2 * (a.nalm + kk); }
-            else { val = 0.5 * P * (s0 - sgn_s * s2); dst = a.alm_out + 2 * (a.nalm + kk) + 1; }
-            // Im g~_l0 and Im c~_l0 vanish exactly (reality condition).
-            if (!(m == 0 && (c & 1))) atomicAdd(dst, val);
-        }
-        __syncthreads();
+        slot ^= 1;
     }
 }
 
@@ -415,9 +465,15 @@ static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out
     return a;
 }
 
-constexpr int kLegR = 4;
-
-int leg_rings_per_item() { return 64 * kLegR; }
+// Rings per lane: 2 unless PSHT_LEG_R (1, 2, 4 or 8) overrides it for tuning runs.
+int leg_rings_per_lane() {
+    static int r = [] {
+        const char *e = getenv("PSHT_LEG_R");
+        int v = e ? atoi(e) : 2;
+        return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 2;
+    }();
+    return r;
+}
 
 // Number of (l, m) coefficient entries with m <= mmax.
 static int64_t leg_entries(const Geometry &g) {
@@ -427,6 +483,22 @@ static int64_t leg_entries(const Geometry &g) {
 
 size_t leg_synth_scratch_bytes(const Geometry &g) { return (size_t)leg_entries(g) * sizeof(double4); }
 
+template <int R>
+static void leg_synth_r(const psht_plan_s &p, const void *Q, double *F, hipStream_t st) {
+    LegArgs a = leg_args<R>(p, Q, nullptr, F);
+    dim3 grid(p.n_leg_items), block(64);
+    if (p.g.spin) hipLaunchKernelGGL((k_leg_synth<R, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_leg_synth<R, false>), grid, block, 0, st, a);
+}
+
+template <int R>
+static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, hipStream_t st) {
+    LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
+    dim3 grid(p.n_leg_items), block(64);
+    if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_leg_adjoint<R, false>), grid, block, 0, st, a);
+}
+
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, hipStream_t st) {
     if (p.n_leg_items == 0) return hipSuccess;
     const Geometry &g = p.g;
@@ -435,19 +507,23 @@ hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, vo
     const double2 *gg = static_cast<const double2 *>(alm);
     hipLaunchKernelGGL(k_leg_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gg, gg + nalm,
                        reinterpret_cast<const double4 *>(p.leg->d_coef), static_cast<double4 *>(scratch), n, g.lmax);
-    LegArgs a = leg_args<kLegR>(p, scratch, nullptr, F);
-    dim3 grid(p.n_leg_items), block(64);
-    if (g.spin) hipLaunchKernelGGL((k_leg_synth<kLegR, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_leg_synth<kLegR, false>), grid, block, 0, st, a);
+    switch (p.leg_rings_per_item / 64) {
+        case 1: leg_synth_r<1>(p, scratch, F, st); break;
+        case 2: leg_synth_r<2>(p, scratch, F, st); break;
+        case 8: leg_synth_r<8>(p, scratch, F, st); break;
+        default: leg_synth_r<4>(p, scratch, F, st); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, hipStream_t st) {
     if (p.n_leg_items == 0) return hipSuccess;
-    LegArgs a = leg_args<kLegR>(p, nullptr, alm, const_cast<double *>(F));
-    dim3 grid(p.n_leg_items), block(64);
-    if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<kLegR, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_leg_adjoint<kLegR, false>), grid, block, 0, st, a);
+    switch (p.leg_rings_per_item / 64) {
+        case 1: leg_adjoint_r<1>(p, F, alm, st); break;
+        case 2: leg_adjoint_r<2>(p, F, alm, st); break;
+        case 8: leg_adjoint_r<8>(p, F, alm, st); break;
+        default: leg_adjoint_r<4>(p, F, alm, st); break;
+    }
     return hipGetLastError();
 }
 

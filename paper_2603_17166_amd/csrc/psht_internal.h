@@ -153,8 +153,8 @@ hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n,
 hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
                              int32_t *d_cursor, hipStream_t st);
 
-// Rings handled by one Legendre work item (64 lanes x rings per lane).
-int leg_rings_per_item();
+// Rings per lane of the Legendre kernels (a work item covers 64 x this many rings).
+int leg_rings_per_lane();
 
 // Largest FFT length one workgroup transforms in LDS.
 constexpr int kFftMaxLds64 = 8192;
