@@ -74,87 +74,208 @@ def cpu_baseline(w, n_sample: int) -> dict:
                       "(synth %.1f s, adjoint %.1f s)" % (idx.shape[0], t1 - t0, t2 - t1)}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=512)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check-points", type=int, default=64, help="oracle check of the synthesized map")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
-        return 2
+def stage_avgs(stages: dict) -> dict:
+    return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
 
+
+def roofline(w, info, avg: dict) -> dict:
+    """Roofline of the dominant kernel from live HIP-event timings."""
+    dom = max(avg, key=lambda k: avg[k])
+    W = info["nufft_w"]
+    if dom in ("leg_synth", "leg_adj"):
+        flops = info["legendre_triples"] * leg_flops_per_triple(w.spin)
+        roof = {"bound": "alu", "achieved": flops / (avg[dom] * 1e-3) / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "work": "%.4g FLOP per launch (%d per (ring, m, l) triple)" % (
+                    flops, leg_flops_per_triple(w.spin))}
+    elif dom in ("interp", "spread") and not info["map_is_fp32"]:
+        flops = w.npoints * nufft_flops_per_point(W)
+        roof = {"bound": "alu", "achieved": flops / (avg[dom] * 1e-3) / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "work": "%.4g FLOP per launch (%d per point)" % (flops, nufft_flops_per_point(W))}
+    else:
+        cs = 8 if info["map_is_fp32"] else 16
+        grid = info["rows_used"] * info["nphi_grid"] * cs
+        nbytes = grid + w.npoints * (16 + 4 + cs)
+        roof = {"bound": "hbm", "achieved": nbytes / (avg[dom] * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "work": "%.4g B per launch" % nbytes}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launch_ms"] = avg[dom]
+    return roof
+
+
+def time_steps(plan, a, fmap, out_map, out_alm, steps: int, which: str) -> float:
+    """Seconds for `steps` calls of synth, adjoint or both, bracketed by device synchronisation."""
     import torch
 
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        if which in ("synth", "both"):
+            plan.synth(a, out=out_map)
+        if which in ("adjoint", "both"):
+            plan.adjoint(fmap, out=out_alm)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def oracle_error(w, a_np, out_map, n: int) -> float:
     import oracle
+
+    idx = w.subsample(n)
+    ref = oracle.synth(a_np, w.theta[idx], w.phi[idx], w.lmax, w.spin)
+    got = out_map.cpu().numpy()[idx].astype(np.complex128)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def run_transform(w, steps: int, warmup: int, check_points: int, log) -> dict:
+    """Plan, warm up, time synth+adjoint steps (with per-stage HIP events) and
+    synth-only / adjoint-only loops; oracle error on a subsample."""
+    import torch
+
     from paper_2603_17166_amd.plan import Plan
 
-    torch.cuda.set_device(0)
-    w = WORKLOADS[args.workload]()
     a_np = w.alm()
     t0 = time.perf_counter()
     plan = Plan(w.theta, w.phi, w.lmax, w.spin, w.epsilon, w.precision)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info
+    log("plan %s: %.2f s, Lmax %d mmax %d W %d" % (w.name, plan_s, info["Lmax"], info["mmax"], info["nufft_w"]))
     a = torch.as_tensor(a_np, device="cuda")
     fmap = torch.as_tensor(w.adjoint_map(np.complex64 if info["map_is_fp32"] else np.complex128), device="cuda")
     out_map = torch.empty(w.npoints, dtype=plan.map_dtype, device="cuda")
     out_alm = torch.empty_like(a)
     plan.workspace(1)
-
-    for _ in range(args.warmup):
-        plan.synth(a, out=out_map)
-        plan.adjoint(fmap, out=out_alm)
-    torch.cuda.synchronize()
-
+    time_steps(plan, a, fmap, out_map, out_alm, warmup, "both")
     plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.synth(a, out=out_map)
-        plan.adjoint(fmap, out=out_alm)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = plan.timing()
+    t_both = time_steps(plan, a, fmap, out_map, out_alm, steps, "both")
+    avg = stage_avgs(plan.timing())
     plan.set_timing(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = w.npoints / (ms_per_step * 1e-3)
+    t_syn = time_steps(plan, a, fmap, out_map, out_alm, steps, "synth")
+    t_adj = time_steps(plan, a, fmap, out_map, out_alm, steps, "adjoint")
+    err = oracle_error(w, a_np, out_map, check_points)
+    res = {"plan": plan, "info": info, "plan_s": plan_s, "ms_per_step": t_both * 1e3 / steps, "avg": avg,
+           "synth_ms": t_syn * 1e3 / steps, "adjoint_ms": t_adj * 1e3 / steps, "rel_err": err}
+    log("%s: %.3f ms/step (synth %.3f, adjoint %.3f), rel err %.2e" % (
+        w.name, res["ms_per_step"], res["synth_ms"], res["adjoint_ms"], err))
+    return res
 
-    # accuracy of this run's synthesis on a seeded subsample
-    idx = w.subsample(args.check_points)
-    ref = oracle.synth(a_np, w.theta[idx], w.phi[idx], w.lmax, w.spin)
-    got = out_map.cpu().numpy()[idx].astype(np.complex128)
-    rel_err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
-    # roofline of the dominant kernel
-    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
-    dom = max(avg, key=lambda k: avg[k])
-    W = info["nufft_w"]
-    if dom in ("leg_synth", "leg_adj"):
-        flops = info["legendre_triples"] * leg_flops_per_triple(w.spin)
-        roof = {"bound": "alu", "achieved": flops / (avg[dom] * 1e-3) / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                "unit": "TFLOP/s"}
-    elif dom in ("interp", "spread") and not info["map_is_fp32"]:
-        flops = w.npoints * nufft_flops_per_point(W)
-        roof = {"bound": "alu", "achieved": flops / (avg[dom] * 1e-3) / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                "unit": "TFLOP/s"}
-    else:
-        cs = 8 if info["map_is_fp32"] else 16
-        grid = info["rows_used"] * info["nphi_grid"] * cs
-        nbytes = grid + w.npoints * (16 + 4 + cs)
-        roof = {"bound": "hbm", "achieved": nbytes / (avg[dom] * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
+def precision_form(steps: int, check_points: int, log) -> dict:
+    """FP32 (eps 1e-5) vs FP64 (eps 1e-10) on the 1501 deg^2, lmax 4096 patch."""
+    out = {}
+    for prec in ("fp32", "fp64"):
+        w = syn.spt_fine(prec)
+        r = run_transform(w, steps, 2, check_points, log)
+        out[prec] = {"epsilon": w.epsilon, "points_per_s": w.npoints / (r["ms_per_step"] * 1e-3),
+                     "ms_per_step": r["ms_per_step"], "synth_ms": r["synth_ms"], "adjoint_ms": r["adjoint_ms"],
+                     "rel_err_vs_oracle": r["rel_err"], "plan_s": r["plan_s"],
+                     "stage_ms": {k: round(v, 4) for k, v in r["avg"].items()}}
+        r["plan"].close()
+    out["workload"] = "spt1501-l4096-s2 (%d points)" % syn.spt_fine("fp32").npoints
+    out["fp32_speedup"] = out["fp32"]["points_per_s"] / out["fp64"]["points_per_s"]
+    return out
 
+
+def served(n_requests: int, load: float, log) -> dict:
+    """Served mix: discs of 2/5/10/20 deg, lmax 512..4096, spin 0/2, 50/50 synth/adjoint, FP32 eps 1e-5."""
+    import torch
+
+    from paper_2603_17166_amd.serve import (PlanKey, Server, TorchExecutor, latency_stats, poisson_arrivals,
+                                            run_closed_loop, run_open_loop)
+
+    eps = 1e-5
+    ex = TorchExecutor(n_slots=4)
+    npts = {}
+    maps = {}
+    for r in syn.SERVED_RADII:
+        th, ph = syn.served_patch(r)
+        ex.add_patch("disc%g" % r, th, ph)
+        npts[r] = th.shape[0]
+        maps[r] = torch.as_tensor(syn.gaussian_map(th.shape[0], syn.SEED_MAP + 4 + int(r), np.complex64), device="cuda")
+    alms = {}
+    for lmax in syn.SERVED_LMAX:
+        for spin in syn.SERVED_SPINS:
+            alms[(lmax, spin)] = torch.as_tensor(syn.gaussian_alm(lmax, spin, syn.SEED_ALM + 4 + lmax + spin),
+                                                 device="cuda")
+
+    def specs_of(mix):
+        out = []
+        for radius, lmax, spin, op, _ in mix:
+            key = PlanKey("disc%g" % radius, lmax, spin, eps, "fp32")
+            out.append((key, op, alms[(lmax, spin)] if op == "synth" else maps[radius]))
+        return out
+
+    srv = Server(ex, memory_budget=96 << 30, n_slots=4, max_batch=4)
+    # warm-up: every combination once (creates and caches all plans)
+    t0 = time.perf_counter()
+    combos = [(r, l, s, op, 0) for r in syn.SERVED_RADII for l in syn.SERVED_LMAX for s in syn.SERVED_SPINS
+              for op in ("synth", "adjoint")]
+    run_closed_loop(srv, specs_of(combos))
+    torch.cuda.synchronize()
+    log("served: %d plans created in %.1f s" % (srv.plans_created, time.perf_counter() - t0))
+    mix = specs_of(syn.served_mix(n_requests, seed=syn.SEED_MAP + 4))
+    reqs, secs = run_closed_loop(srv, mix)
+    sat = len(reqs) / secs
+    log("served: saturation %.1f requests/s" % sat)
+    rate = load * sat
+    offs = poisson_arrivals(len(mix), rate, syn.SEED_MAP + 44)
+    reqs = run_open_loop(srv, mix, offs)
+    torch.cuda.synchronize()
+    st = latency_stats(reqs)
+    pts = sum(npts[float(r.key.patch[4:])] for r in reqs)
+    span = max(r.t_done for r in reqs) - min(r.t_arrival for r in reqs)
+    st.update({"load": load, "arrival_rate_per_s": rate, "saturation_requests_per_s": sat,
+               "points_per_s": pts / span, "saturation_points_per_s": pts / secs, "batches": srv.n_batches,
+               "max_concurrent": srv.max_concurrent, "plans_resident": len(srv.plans),
+               "resident_gb": srv.resident / 1e9, "errors": sum(1 for r in reqs if r.error)})
+    log("served at %.1fx saturation: p50 %.2f ms, p99 %.2f ms" % (load, st["p50_ms"], st["p99_ms"]))
+    srv.close()
+    return st
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", type=int, default=1536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-points", type=int, default=64, help="oracle check of the synthesized map")
+    ap.add_argument("--no-extras", action="store_true", help="skip the precision-form and served-mix runs")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: there is no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
+        return 0
+    w = WORKLOADS[args.workload]()
+    r = run_transform(w, args.steps, args.warmup, args.check_points, log)
+    info, avg = r["info"], r["avg"]
+    ms_per_step = r["ms_per_step"]
     line = {
         "metric": "synth+adjoint points/s at eps=1e-10 FP64 vs eps=1e-5 FP32; p50/p99 latency",
-        "value": value,
+        "value": w.npoints / (ms_per_step * 1e-3),
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -166,17 +287,25 @@ def main() -> int:
         "dtype": "f32" if info["map_is_fp32"] else "f64",
         "data": "synthetic (seeded points and coefficients)",
         "config": {"workload": w.name, "npoints": w.npoints, "lmax": w.lmax, "spin": w.spin, "epsilon": w.epsilon,
-                   "precision": w.precision, "Lmax": info["Lmax"], "mmax": info["mmax"], "nufft_w": W,
+                   "precision": w.precision, "Lmax": info["Lmax"], "mmax": info["mmax"], "nufft_w": info["nufft_w"],
                    "grid": [info["rows_used"], info["nphi_grid"]], "legendre_triples": info["legendre_triples"]},
-        "rel_err_vs_oracle": rel_err,
-        "plan_s": plan_s,
+        "synth_points_per_s": w.npoints / (r["synth_ms"] * 1e-3),
+        "adjoint_points_per_s": w.npoints / (r["adjoint_ms"] * 1e-3),
+        "transforms_per_s": 2.0 / (ms_per_step * 1e-3),
+        "rel_err_vs_oracle": r["rel_err"],
+        "plan_s": r["plan_s"],
         "stage_ms": {k: round(avg[k], 4) for k in avg},
-        "roofline": roof,
+        "roofline": roofline(w, info, avg),
     }
+    r["plan"].close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        log("cpu baseline: %.1f points/s" % line["cpu_baseline"]["value"])
+    if not args.no_extras:
+        line["precision_form"] = precision_form(max(3, args.steps // 4), 32, log)
+        line["served"] = served(args.serve_requests, args.serve_load, log)
+        line["served_vs_fp64_single"] = line["served"]["points_per_s"] / line["value"]
     print(json.dumps(line), flush=True)
-    plan.close()
     return 0
 
 

@@ -125,6 +125,27 @@ psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map,
 psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm,
                          void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* Gradient forms for automatic differentiation of a real loss L.  Gradients
+ * of complex quantities follow the convention dL/dRe z + i dL/dIm z.
+ *
+ * psht_adjoint_grad: given map_grad = dL/df for f = psht_synth(alm), writes
+ * alm_grad = dL/dalm.  Because synthesis is real-linear in (Re, Im) of every
+ * entry and the coefficient inner product above weighs orders m >= 1 twice,
+ * this is the adjoint synthesis (Sec. I) with the outputs of every m >= 1
+ * doubled; m = 0 entries are real (their imaginary parts do not enter the
+ * synthesis) and entries with l < s are zero.
+ *
+ * psht_synth_grad: given alm_grad = dL/da~ for a~ = psht_adjoint(map),
+ * writes map_grad = dL/dmap: the synthesis (eq. syn) of alm_grad with every
+ * order m >= 1 halved (Im of the m = 0 entries is ignored, as in synthesis).
+ *
+ * Same layouts, workspace rule, precision and errors as psht_synth /
+ * psht_adjoint; the two cost what the plain transforms cost. */
+psht_status psht_adjoint_grad(psht_plan plan, int nmaps, const void *map_grad, void *alm_grad,
+                              void *workspace, size_t ws_bytes, void *hip_stream);
+psht_status psht_synth_grad(psht_plan plan, int nmaps, const void *alm_grad, void *map_grad,
+                            void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Free the plan's device memory.  The caller must synchronise every stream
  * that still runs work of this plan first.  NULL is a no-op. */
 void psht_plan_destroy(psht_plan plan);

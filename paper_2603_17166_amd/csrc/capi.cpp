@@ -291,8 +291,12 @@ psht_status psht_plan_query(psht_plan plan, psht_plan_info *info) {
     return PSHT_OK;
 }
 
-psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
-                       void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+psht_status synth_impl(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
+                       double mscale, void *hip_stream) {
     if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
     if (nmaps < 0) return fail(PSHT_ERR_ARG, "nmaps < 0");
     if (nmaps > 0 && (!alm || (!map && plan->npts > 0))) return fail(PSHT_ERR_ARG, "alm or map is NULL");
@@ -311,7 +315,7 @@ psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, vo
         const void *a = static_cast<const char *>(alm) + i * alm_bytes;
         void *m = static_cast<char *>(map) + i * map_bytes;
         psht_plan_s &P = *plan;
-        hipError_t e = timed(P, PSHT_T_LEG_SYNTH, st, [&] { return psht::launch_leg_synth(P, a, F, Q, st); });
+        hipError_t e = timed(P, PSHT_T_LEG_SYNTH, st, [&] { return psht::launch_leg_synth(P, a, F, Q, mscale, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_THETA_SYNTH, st, [&] { return psht::launch_theta_synth(P, F, V, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_PHI_SYNTH, st, [&] { return psht::launch_phi_synth(P, V, U, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_INTERP, st, [&] { return psht::launch_interp(P, U, m, st); });
@@ -320,8 +324,8 @@ psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, vo
     return PSHT_OK;
 }
 
-psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm, void *workspace, size_t ws_bytes,
-                         void *hip_stream) {
+psht_status adjoint_impl(psht_plan plan, int nmaps, const void *map, void *alm, void *workspace, size_t ws_bytes,
+                         double mscale, void *hip_stream) {
     if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
     if (nmaps < 0) return fail(PSHT_ERR_ARG, "nmaps < 0");
     if (nmaps > 0 && (!alm || (!map && plan->npts > 0))) return fail(PSHT_ERR_ARG, "alm or map is NULL");
@@ -344,10 +348,34 @@ psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm, 
         if (e == hipSuccess) e = timed(P, PSHT_T_PHI_ADJ, st, [&] { return psht::launch_phi_adjoint(P, U, V, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_THETA_ADJ, st, [&] { return psht::launch_theta_adjoint(P, V, F, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_ALM_ZERO, st, [&] { return psht::launch_fill_zero(a, alm_bytes, st); });
-        if (e == hipSuccess) e = timed(P, PSHT_T_LEG_ADJ, st, [&] { return psht::launch_leg_adjoint(P, F, a, st); });
+        if (e == hipSuccess) e = timed(P, PSHT_T_LEG_ADJ, st, [&] { return psht::launch_leg_adjoint(P, F, a, mscale, st); });
         if (e != hipSuccess) return device_fail(e, "adjoint launch");
     }
     return PSHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
+                       void *hip_stream) {
+    return synth_impl(plan, nmaps, alm, map, workspace, ws_bytes, 1.0, hip_stream);
+}
+
+psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm, void *workspace, size_t ws_bytes,
+                         void *hip_stream) {
+    return adjoint_impl(plan, nmaps, map, alm, workspace, ws_bytes, 1.0, hip_stream);
+}
+
+psht_status psht_adjoint_grad(psht_plan plan, int nmaps, const void *map_grad, void *alm_grad, void *workspace,
+                              size_t ws_bytes, void *hip_stream) {
+    return adjoint_impl(plan, nmaps, map_grad, alm_grad, workspace, ws_bytes, 2.0, hip_stream);
+}
+
+psht_status psht_synth_grad(psht_plan plan, int nmaps, const void *alm_grad, void *map_grad, void *workspace,
+                            size_t ws_bytes, void *hip_stream) {
+    return synth_impl(plan, nmaps, alm_grad, map_grad, workspace, ws_bytes, 0.5, hip_stream);
 }
 
 void psht_plan_destroy(psht_plan plan) { free_plan(plan); }
@@ -427,7 +455,7 @@ psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, voi
         void *scratch = nullptr;
         e = hipMalloc(&scratch, std::max<size_t>(16, psht::leg_synth_scratch_bytes(g)));
         if (e == hipSuccess) e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
-        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), scratch, st);
+        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), scratch, 1.0, st);
         if (scratch) {
             hipError_t e2 = hipStreamSynchronize(st);
             if (e == hipSuccess) e = e2;
@@ -435,7 +463,7 @@ psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, voi
         }
     } else if (stage == PSHT_STAGE_LEGENDRE_ADJOINT) {
         e = psht::launch_fill_zero(out, (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16, st);
-        if (e == hipSuccess) e = psht::launch_leg_adjoint(*plan, static_cast<const double *>(in), out, st);
+        if (e == hipSuccess) e = psht::launch_leg_adjoint(*plan, static_cast<const double *>(in), out, 1.0, st);
     } else {
         return fail(PSHT_ERR_ARG, "unknown stage");
     }

@@ -45,6 +45,7 @@ struct LegArgs {
     const double4 *Q;  // synthesis: per (l, m) {Re, Im of P(g + i c), Re, Im of P(conj g + i conj c)}
     double *alm_out;   // adjoint output, complex [2][nalm]
     double *F;         // complex [2 mmax + 1][nring]: synthesis output / adjoint input
+    double mscale;     // adjoint: extra factor on the outputs of order m >= 1
 };
 
 // Block -> item map: the `group` items of one order m run on the same XCD
@@ -68,15 +69,18 @@ __device__ inline void rescale_sel(double &cur, double &prev, int &k) {
 // Per-call combination of the coefficients with the normalisation P_l:
 // Q = P {g_r - c_i, g_i + c_r, g_r + c_i, c_r - g_i} (imaginary parts of the
 // m = 0 coefficients dropped), for every (l, m <= mmax).
-__global__ void k_leg_prep(const double2 *g, const double2 *c, const double4 *coef, double4 *Q, int64_t n, int lmax) {
+__global__ void k_leg_prep(const double2 *g, const double2 *c, const double4 *coef, double4 *Q, int64_t n, int lmax,
+                           double mscale) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double2 a = g[i], b = c[i];
+    double P = coef[i].w;
     if (i <= lmax) {  // m = 0
         a.y = 0.0;
         b.y = 0.0;
+    } else {
+        P *= mscale;
     }
-    const double P = coef[i].w;
     Q[i] = make_double4((a.x - b.y) * P, (a.y + b.x) * P, (a.x + b.y) * P, (b.x - a.y) * P);
 }
 
@@ -425,10 +429,11 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                 const int64_t kk = base + l;
                 double val;
                 double *dst;
-                if (cc == 0) { val = -0.5 * P * (s0 + sgn_s * s2); dst = a.alm_out + 2 * kk; }
-                else if (cc == 1) { val = -0.5 * P * (s1 + sgn_s * s3); dst = a.alm_out + 2 * kk + 1; }
-                else if (cc == 2) { val = -0.5 * P * (s1 - sgn_s * s3); dst = a.alm_out + 2 * (a.nalm + kk); }
-                else { val = 0.5 * P * (s0 - sgn_s * s2); dst = a.alm_out + 2 * (a.nalm + kk) + 1; }
+                const double hP = (m == 0 ? 0.5 : 0.5 * a.mscale) * P;
+                if (cc == 0) { val = -hP * (s0 + sgn_s * s2); dst = a.alm_out + 2 * kk; }
+                else if (cc == 1) { val = -hP * (s1 + sgn_s * s3); dst = a.alm_out + 2 * kk + 1; }
+                else if (cc == 2) { val = -hP * (s1 - sgn_s * s3); dst = a.alm_out + 2 * (a.nalm + kk); }
+                else { val = hP * (s0 - sgn_s * s2); dst = a.alm_out + 2 * (a.nalm + kk) + 1; }
                 // Im g~_l0 and Im c~_l0 vanish exactly (reality condition).
                 if (!(m == 0 && (cc & 1))) atomicAdd(dst, val);
             }
@@ -462,6 +467,7 @@ static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out
     a.Q = static_cast<const double4 *>(Q);
     a.alm_out = static_cast<double *>(const_cast<void *>(alm_out));
     a.F = F;
+    a.mscale = 1.0;
     return a;
 }
 
@@ -492,21 +498,23 @@ static void leg_synth_r(const psht_plan_s &p, const void *Q, double *F, hipStrea
 }
 
 template <int R>
-static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, hipStream_t st) {
+static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
     LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
+    a.mscale = mscale;
     dim3 grid(p.n_leg_items), block(64);
     if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_leg_adjoint<R, false>), grid, block, 0, st, a);
 }
 
-hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, hipStream_t st) {
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, double mscale,
+                            hipStream_t st) {
     if (p.n_leg_items == 0) return hipSuccess;
     const Geometry &g = p.g;
     const int64_t n = leg_entries(g);
     const int64_t nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
     const double2 *gg = static_cast<const double2 *>(alm);
     hipLaunchKernelGGL(k_leg_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gg, gg + nalm,
-                       reinterpret_cast<const double4 *>(p.leg->d_coef), static_cast<double4 *>(scratch), n, g.lmax);
+                       reinterpret_cast<const double4 *>(p.leg->d_coef), static_cast<double4 *>(scratch), n, g.lmax, mscale);
     switch (p.leg_rings_per_item / 64) {
         case 1: leg_synth_r<1>(p, scratch, F, st); break;
         case 2: leg_synth_r<2>(p, scratch, F, st); break;
@@ -516,13 +524,13 @@ hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, vo
     return hipGetLastError();
 }
 
-hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, hipStream_t st) {
+hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
     if (p.n_leg_items == 0) return hipSuccess;
     switch (p.leg_rings_per_item / 64) {
-        case 1: leg_adjoint_r<1>(p, F, alm, st); break;
-        case 2: leg_adjoint_r<2>(p, F, alm, st); break;
-        case 8: leg_adjoint_r<8>(p, F, alm, st); break;
-        default: leg_adjoint_r<4>(p, F, alm, st); break;
+        case 1: leg_adjoint_r<1>(p, F, alm, mscale, st); break;
+        case 2: leg_adjoint_r<2>(p, F, alm, mscale, st); break;
+        case 8: leg_adjoint_r<8>(p, F, alm, mscale, st); break;
+        default: leg_adjoint_r<4>(p, F, alm, mscale, st); break;
     }
     return hipGetLastError();
 }

@@ -134,9 +134,12 @@ namespace psht {
 
 // Stage launchers (defined in the .hip files).  All asynchronous on `st`.
 // Synthesis needs leg_synth_scratch_bytes(g) of scratch (per-call coefficient combinations).
-hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, hipStream_t st);
+// `mscale` multiplies the coefficients (synthesis) or the outputs (adjoint) of
+// every order m >= 1; 1 for the plain transforms.
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, double mscale,
+                            hipStream_t st);
 size_t leg_synth_scratch_bytes(const Geometry &g);
-hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, hipStream_t st);
+hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st);
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st);
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st);
 hipError_t launch_phi_synth(const psht_plan_s &p, const void *V, void *U, hipStream_t st);

@@ -90,8 +90,35 @@ class Plan:
             raise ValueError("alm must have shape (2, nalm) or (nmaps, 2, nalm)")
         return a.contiguous(), single
 
-    def synth(self, alm: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    # `workspace`: optional caller-owned uint8 device tensor of at least
+    # nmaps * workspace_bytes_per_map bytes (calls that overlap on different
+    # streams need distinct workspaces); by default the plan's own one.
+    def synth(self, alm: torch.Tensor, out: torch.Tensor | None = None, stream=None, workspace=None) -> torch.Tensor:
         """Synthesis general (eq. syn): alm (2, nalm) or (nmaps, 2, nalm) complex128 -> map."""
+        return self._synth("psht_synth", alm, out, stream, workspace)
+
+    def synth_grad(self, alm_grad: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                   workspace=None) -> torch.Tensor:
+        """Gradient w.r.t. the map of a real loss of adjoint(map), from its gradient w.r.t. the adjoint's output."""
+        return self._synth("psht_synth_grad", alm_grad, out, stream, workspace)
+
+    def adjoint(self, fmap: torch.Tensor, out: torch.Tensor | None = None, stream=None, workspace=None) -> torch.Tensor:
+        """Adjoint synthesis general: map (npts,) or (nmaps, npts) -> alm (.., 2, nalm) complex128."""
+        return self._adjoint("psht_adjoint", fmap, out, stream, workspace)
+
+    def adjoint_grad(self, map_grad: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                     workspace=None) -> torch.Tensor:
+        """Gradient w.r.t. alm of a real loss of synth(alm), from its gradient w.r.t. the synthesized map."""
+        return self._adjoint("psht_adjoint_grad", map_grad, out, stream, workspace)
+
+    def _workspace_for(self, nm: int, workspace):
+        if workspace is None:
+            return self.workspace(nm)
+        if workspace.dtype != torch.uint8 or workspace.device != self.device or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on %s" % self.device)
+        return workspace
+
+    def _synth(self, fn: str, alm: torch.Tensor, out, stream, workspace) -> torch.Tensor:
         a, single = self._alm_in(alm)
         nm = a.shape[0]
         if out is None:
@@ -100,14 +127,13 @@ class Plan:
             out = out.view(nm, self.npoints)
             if out.dtype != self.map_dtype or not out.is_contiguous():
                 raise ValueError("out must be a contiguous %s tensor" % self.map_dtype)
-        ws = self.workspace(nm)
+        ws = self._workspace_for(nm, workspace)
         with torch.cuda.device(self.device):
-            _lib.check(_lib.load().psht_synth(self._h, nm, a.data_ptr(), out.data_ptr() or None, ws.data_ptr(),
-                                              ws.numel(), _stream(stream)))
+            _lib.check(getattr(_lib.load(), fn)(self._h, nm, a.data_ptr(), out.data_ptr() or None, ws.data_ptr(),
+                                                ws.numel(), _stream(stream)))
         return out[0] if single else out
 
-    def adjoint(self, fmap: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """Adjoint synthesis general: map (npts,) or (nmaps, npts) -> alm (.., 2, nalm) complex128."""
+    def _adjoint(self, fn: str, fmap: torch.Tensor, out, stream, workspace) -> torch.Tensor:
         if fmap.dtype != self.map_dtype:
             raise TypeError("map must be %s for this plan" % self.map_dtype)
         if fmap.device != self.device:
@@ -119,9 +145,13 @@ class Plan:
         nm = f.shape[0]
         if out is None:
             out = torch.empty((nm, 2, nalm(self.lmax)), dtype=torch.complex128, device=self.device)
-        ws = self.workspace(nm)
+        else:
+            if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() != nm * 2 * nalm(self.lmax):
+                raise ValueError("out must be a contiguous complex128 tensor of %d elements" % (nm * 2 * nalm(self.lmax)))
+            out = out.view(nm, 2, nalm(self.lmax))
+        ws = self._workspace_for(nm, workspace)
         with torch.cuda.device(self.device):
-            _lib.check(_lib.load().psht_adjoint(self._h, nm, f.data_ptr() or None, out.data_ptr(), ws.data_ptr(),
+            _lib.check(getattr(_lib.load(), fn)(self._h, nm, f.data_ptr() or None, out.data_ptr(), ws.data_ptr(),
                                                 ws.numel(), _stream(stream)))
         return out[0] if single else out
 

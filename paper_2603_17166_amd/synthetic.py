@@ -66,6 +66,12 @@ def gaussian_map(n: int, seed: int, dtype=np.complex128) -> np.ndarray:
     return (r.standard_normal(n) + 1j * r.standard_normal(n)).astype(dtype)
 
 
+def complex_noise(n: int, sigma: float, seed: int) -> np.ndarray:
+    """Complex white noise with E|n|^2 = sigma^2 (variance sigma^2 / 2 per real part)."""
+    r = rng(seed)
+    return (r.standard_normal(n) + 1j * r.standard_normal(n)) * (sigma / math.sqrt(2.0))
+
+
 def uniform_cap(n: int, radius: float, seed: int):
     """n points uniform in the spherical cap theta <= radius around the pole."""
     r = rng(seed)
@@ -223,18 +229,44 @@ def spt_like(lmax: int = 2048) -> Workload:
     return Workload("spt1658-l%d-s2-fp64" % lmax, lmax, 2, 1e-10, "fp64", th, ph, 2)
 
 
+_POINTS: dict = {}  # point sets shared by workloads that differ only in precision
+
+
 def spt_fine(precision: str = "fp32") -> Workload:
     """Spin-2, lmax 4096: RA [-48.4,48.4] x Dec [-70,-42] deg (~1501 deg^2)
     at 0.5', 2.5' RMS jitter (~21.6M points); eps 1e-5 FP32 or 1e-10 FP64."""
-    th, ph = rect_patch(48.4, -70.0, -42.0, 0.5, 2.5, SEED_POINTS + 3)
+    if "spt_fine" not in _POINTS:
+        _POINTS["spt_fine"] = rect_patch(48.4, -70.0, -42.0, 0.5, 2.5, SEED_POINTS + 3)
+    th, ph = _POINTS["spt_fine"]
     eps = 1e-5 if precision == "fp32" else 1e-10
     return Workload("spt1501-l4096-s2-%s" % precision, 4096, 2, eps, precision, th, ph, 3)
 
 
+SERVED_RADII = (2.0, 5.0, 10.0, 20.0)
+SERVED_LMAX = (512, 1024, 2048, 4096)
+SERVED_SPINS = (0, 2)
+
+
+def served_patch(radius_deg: float, res_arcmin: float = 1.0):
+    """Point set of one served disc: polar disc at `res` (1') with 2.5' jitter."""
+    return disc_patch(radius_deg, res_arcmin, 2.5, SEED_POINTS + 4 + int(round(radius_deg * 100)))
+
+
+def served_mix(n: int, seed: int = SEED_MAP + 4, radii=SERVED_RADII, lmaxes=SERVED_LMAX, spins=SERVED_SPINS):
+    """n requests of the served mix: (radius, lmax, spin, op, data seed), uniform
+    over the radius x lmax x spin combinations, 50/50 synthesis / adjoint."""
+    r = rng(seed)
+    out = []
+    for i in range(n):
+        out.append((float(radii[r.integers(len(radii))]), int(lmaxes[r.integers(len(lmaxes))]),
+                    int(spins[r.integers(len(spins))]), "synth" if r.integers(2) == 0 else "adjoint",
+                    int(seed * 7919 + i)))
+    return out
+
+
 def served_disc(radius_deg: float, lmax: int, spin: int) -> Workload:
-    """One member of the served mix: polar disc at 1' with 2.5' jitter, FP32 eps 1e-5."""
-    key = int(radius_deg * 100) * 100000 + lmax * 10 + spin
-    th, ph = disc_patch(radius_deg, 1.0, 2.5, SEED_POINTS + 4 + key)
+    """One member of the served mix as a stand-alone workload (FP32, eps 1e-5)."""
+    th, ph = served_patch(radius_deg)
     return Workload("disc%g-l%d-s%d-fp32" % (radius_deg, lmax, spin), lmax, spin, 1e-5, "fp32", th, ph, 4)
 
 

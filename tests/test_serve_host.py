@@ -1,0 +1,211 @@
+"""Scheduling logic of the serving form, on the CPU with a simulated executor:
+continuous admission, batching by (plan, operation), slot and memory limits,
+LRU plan eviction, error paths and latency statistics."""
+import math
+
+import pytest
+
+from paper_2603_17166_amd.serve import (PlanKey, Server, latency_stats, percentile, poisson_arrivals,
+                                        run_closed_loop, run_open_loop)
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Batches take `cost(key, op, n)` seconds of simulated time; the result of
+    each request is (rid tag, op, plan key) so routing can be checked."""
+
+    def __init__(self, clock, plan_bytes=100, per_map=10, cost=None, fail_patch=None):
+        self.clock = clock
+        self.plan_bytes = plan_bytes
+        self.per_map = per_map
+        self.cost = cost or (lambda key, op, n: 1.0 + 0.1 * n)
+        self.fail_patch = fail_patch
+        self.live_plans = set()
+        self.created = []
+        self.launches = []
+        self.running = []
+
+    def plan_bytes_estimate(self, key):
+        return self.plan_bytes
+
+    def create_plan(self, key):
+        if key.patch == self.fail_patch:
+            raise ValueError("bad patch")
+        self.created.append(key)
+        self.live_plans.add(key)
+        return key, self.plan_bytes
+
+    def drop_plan(self, h):
+        self.live_plans.remove(h)
+
+    def footprint(self, h, op, n):
+        return n * self.per_map
+
+    def launch(self, h, op, inputs, slot):
+        assert h in self.live_plans
+        tok = {"end": self.clock() + self.cost(h, op, len(inputs)), "out": [(x, op, h) for x in inputs], "slot": slot}
+        self.launches.append((h, op, len(inputs), slot, self.clock()))
+        self.running.append(tok)
+        return tok
+
+    def ready(self, tok):
+        return self.clock() >= tok["end"]
+
+    def results(self, tok):
+        return tok["out"]
+
+    def release(self, tok):
+        self.running.remove(tok)
+
+    def wait(self, toks, poll):
+        # advance simulated time to the next completion
+        self.clock.t = max(self.clock.t, min(t["end"] for t in toks))
+
+
+def K(p="a", l=64, s=0):
+    return PlanKey(p, l, s, 1e-5, "fp32")
+
+
+def test_results_routed_and_batched():
+    c = Clock()
+    ex = FakeExecutor(c)
+    srv = Server(ex, memory_budget=10_000, n_slots=2, max_batch=3, clock=c)
+    reqs = [srv.submit(K("a"), "synth", i) for i in range(5)] + [srv.submit(K("b"), "adjoint", 10 + i) for i in range(2)]
+    srv.run_until_idle()
+    for r in reqs:
+        assert r.result == (r.data, r.op, r.key)
+        assert r.error is None and r.done
+    sizes = sorted(n for _, _, n, _, _ in ex.launches)
+    assert sizes == [2, 2, 3]  # a:3 + a:2 (head first, FIFO), b:2
+    assert srv.max_concurrent == 2
+
+
+def test_fifo_head_first_and_slot_limit():
+    c = Clock()
+    ex = FakeExecutor(c)
+    srv = Server(ex, memory_budget=10_000, n_slots=1, max_batch=4, clock=c)
+    r1 = srv.submit(K("a"), "synth", 1)
+    r2 = srv.submit(K("b"), "synth", 2)
+    r3 = srv.submit(K("a"), "synth", 3)
+    srv.step()
+    assert len(srv.inflight) == 1 and r1.batch_size == 2 and r3.batch_size == 2  # same plan/op joins the head
+    assert math.isnan(r2.t_admit)
+    srv.run_until_idle()
+    assert r2.t_admit >= r1.t_done
+    assert max(len(ex.running), 0) == 0
+
+
+def test_continuous_admission_while_running():
+    """A request that arrives while a batch runs starts as soon as a slot is free,
+    without waiting for the running batch."""
+    c = Clock()
+    ex = FakeExecutor(c, cost=lambda k, op, n: 10.0 if k.patch == "big" else 1.0)
+    srv = Server(ex, memory_budget=10_000, n_slots=2, max_batch=4, clock=c)
+    big = srv.submit(K("big"), "synth", 0)
+    srv.step()
+    c.t = 2.0
+    small = srv.submit(K("small"), "adjoint", 1)
+    srv.step()
+    assert small.t_admit == 2.0
+    srv.run_until_idle()
+    assert small.t_done == 3.0 and big.t_done == 10.0
+    assert small.latency == pytest.approx(1.0)
+
+
+def test_memory_budget_never_exceeded_and_lru_eviction():
+    c = Clock()
+    ex = FakeExecutor(c, plan_bytes=100, per_map=30)
+    # room for two plans plus one batch of 3 maps at most
+    srv = Server(ex, memory_budget=290, n_slots=4, max_batch=8, clock=c)
+    seen = []
+    orig = srv._admit_head
+
+    def admit():
+        ok = orig()
+        seen.append(srv._used())
+        return ok
+    srv._admit_head = admit
+    keys = [K(p) for p in "abcab"]
+    reqs = [srv.submit(k, "synth", i) for i, k in enumerate(keys) for _ in range(4)]
+    srv.run_until_idle()
+    assert all(r.error is None for r in reqs)
+    assert max(seen) <= 290 and srv.peak_bytes <= 290
+    assert srv.plans_evicted >= 1
+    assert len(ex.live_plans) <= 2
+
+
+def test_request_too_large_fails_cleanly():
+    c = Clock()
+    ex = FakeExecutor(c, plan_bytes=100, per_map=1000)
+    srv = Server(ex, memory_budget=500, n_slots=2, clock=c)
+    r = srv.submit(K("a"), "synth", 0)
+    ok = srv.submit(K("b"), "synth", 1)
+    ex.per_map = 1000
+    srv.run_until_idle()
+    assert r.error is not None and "memory budget" in r.error
+    assert ok.error is not None  # same footprint rule
+    ex2 = FakeExecutor(c, plan_bytes=600)
+    srv2 = Server(ex2, memory_budget=500, n_slots=2, clock=c)
+    r2 = srv2.submit(K("a"), "synth", 0)
+    srv2.run_until_idle()
+    assert "memory budget" in r2.error
+
+
+def test_plan_creation_error_fails_only_that_request():
+    c = Clock()
+    ex = FakeExecutor(c, fail_patch="bad")
+    srv = Server(ex, memory_budget=10_000, clock=c)
+    bad = srv.submit(K("bad"), "synth", 0)
+    good = srv.submit(K("a"), "synth", 1)
+    srv.run_until_idle()
+    assert "plan creation failed" in bad.error
+    assert good.error is None and good.result[0] == 1
+
+
+def test_invalid_op_rejected():
+    srv = Server(FakeExecutor(Clock()), memory_budget=100)
+    with pytest.raises(ValueError):
+        srv.submit(K(), "inverse", 0)
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(Clock()), memory_budget=0)
+
+
+def test_open_loop_poisson_stats():
+    c = Clock()
+    ex = FakeExecutor(c, cost=lambda k, op, n: 0.01 * n)
+    srv = Server(ex, memory_budget=1 << 30, n_slots=2, max_batch=4, clock=c)
+    offs = poisson_arrivals(400, 50.0, 7)
+    assert all(b > a for a, b in zip(offs, offs[1:]))
+    assert abs(len(offs) / offs[-1] - 50.0) < 10.0
+    specs = [(K("ab"[i % 2]), "synth" if i % 3 else "adjoint", i) for i in range(400)]
+
+    # the simulated clock moves only through executor waits; advance it to the next arrival too
+    import paper_2603_17166_amd.serve as sv
+    real_sleep = sv.time.sleep
+    sv.time.sleep = lambda dt: setattr(c, "t", c.t + dt)
+    try:
+        reqs = run_open_loop(srv, specs, offs)
+    finally:
+        sv.time.sleep = real_sleep
+    st = latency_stats(reqs, skip=20)
+    assert st["n"] == 380
+    assert st["p50_ms"] <= st["p99_ms"]
+    assert all(r.result[0] == r.data for r in reqs)
+    assert all(r.latency >= 0.0 for r in reqs)
+
+
+def test_closed_loop_and_percentiles():
+    c = Clock()
+    ex = FakeExecutor(c, cost=lambda k, op, n: 1.0)
+    srv = Server(ex, memory_budget=1 << 30, n_slots=2, max_batch=2, clock=c)
+    reqs, secs = run_closed_loop(srv, [(K(), "synth", i) for i in range(8)])
+    assert secs == pytest.approx(2.0)  # 4 batches of 2 on 2 slots
+    assert percentile([3, 1, 2, 4], 50) == 2 and percentile([3, 1, 2, 4], 100) == 4
+    assert percentile(list(range(1, 101)), 99) == 99
