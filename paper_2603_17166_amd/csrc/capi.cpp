@@ -3,6 +3,8 @@
 // layout and the stage sequences of synthesis and adjoint synthesis.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -234,7 +236,15 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         return fail(PSHT_ERR_NOMEM, "FFT tables");
     if (p.phi_split && !make_fft_table(p, p.fft_np_half, g.Nphi / 2, st)) return fail(PSHT_ERR_NOMEM, "FFT tables");
 
-    // points: bucket sort into tiles
+    // points: bucket sort into tiles (PSHT_TILE="<rows>x<cols>" overrides the tile shape for tuning runs)
+    if (const char *ts = getenv("PSHT_TILE")) {
+        int tx = 0, ty = 0;
+        if (sscanf(ts, "%dx%d", &tx, &ty) == 2 && tx >= 4 && ty >= 8 && tx <= 64 && ty <= 128 &&
+            (size_t)(tx + g.W - 1) * ((ty + g.W - 1) | 1) * 16 <= 65536) {
+            p.tile_x = tx;
+            p.tile_y = ty;
+        }
+    }
     p.ntx = (g.rows_used + p.tile_x - 1) / p.tile_x;
     p.nty = (g.Nphi + p.tile_y - 1) / p.tile_y;
     p.ntiles = p.ntx * p.nty;
@@ -242,11 +252,17 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         !dalloc(p, p.d_perm, (size_t)npoints) || !dalloc(p, p.d_tile_start, (size_t)p.ntiles + 1))
         return fail(PSHT_ERR_NOMEM, "allocating sorted points");
     {
-        ScopedDevFree keys, cursor;
-        hipError_t e = hipMalloc(&keys.p, sizeof(int32_t) * std::max<int64_t>(npoints, 1));
+        ScopedDevFree keys, cursor, tpx, tpy, tperm;
+        const size_t nn = (size_t)std::max<int64_t>(npoints, 1);
+        hipError_t e = hipMalloc(&keys.p, sizeof(int32_t) * nn);
         if (e == hipSuccess) e = hipMalloc(&cursor.p, sizeof(int32_t) * (size_t)p.ntiles);
+        if (e == hipSuccess) e = hipMalloc(&tpx.p, sizeof(double) * nn);
+        if (e == hipSuccess) e = hipMalloc(&tpy.p, sizeof(double) * nn);
+        if (e == hipSuccess) e = hipMalloc(&tperm.p, sizeof(int32_t) * nn);
         if (e != hipSuccess) return device_fail(e, "sort scratch");
-        e = psht::launch_point_sort(p, theta, phi, static_cast<int32_t *>(keys.p), static_cast<int32_t *>(cursor.p), st);
+        e = psht::launch_point_sort(p, theta, phi, static_cast<int32_t *>(keys.p), static_cast<int32_t *>(cursor.p),
+                                    static_cast<double *>(tpx.p), static_cast<double *>(tpy.p),
+                                    static_cast<int32_t *>(tperm.p), st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return device_fail(e, "point sort");
     }

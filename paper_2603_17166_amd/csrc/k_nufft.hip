@@ -14,7 +14,8 @@
 // tile_x x tile_y stencil origins, so its points touch a (tile_x + W - 1) x
 // (tile_y + W - 1) subgrid.  One workgroup per tile stages that subgrid in
 // LDS: interpolation reads it once from HBM; spreading accumulates into it
-// with LDS atomics and flushes it with one global atomic per cell.
+// (in double) with LDS atomics and flushes it with one global atomic per
+// non-zero cell and component.
 #include "psht_internal.h"
 
 namespace psht {
@@ -115,10 +116,12 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
     const int tx = t / a.nty, ty = t - tx * a.nty;
     const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1;
     const int SYP = SY | 1;  // odd row stride spreads neighbouring rows over the LDS banks
-    // separate real and imaginary planes: one 8-byte atomic per lane per instruction
-    T *Sre = reinterpret_cast<T *>(smem), *Sim = Sre + SX * SYP;
+    // Separate real and imaginary planes, accumulated in double for both map
+    // precisions: the FP64 LDS atomic add is a native fast path on gfx950,
+    // while FP32 LDS atomic adds measured an order of magnitude slower.
+    double *Sre = reinterpret_cast<double *>(smem), *Sim = Sre + SX * SYP;
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
-    for (int e = threadIdx.x; e < 2 * SX * SYP; e += kTileThreads) Sre[e] = (T)0;
+    for (int e = threadIdx.x; e < 2 * SX * SYP; e += kTileThreads) Sre[e] = 0.0;
     __syncthreads();
     for (int p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
         const double X = a.px[p], Y = a.py[p];
@@ -134,12 +137,12 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         const double fr = f.x, fi = f.y;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            T *Rre = Sre + (li + i) * SYP + lj, *Rim = Sim + (li + i) * SYP + lj;
+            double *Rre = Sre + (li + i) * SYP + lj, *Rim = Sim + (li + i) * SYP + lj;
             const double wr = kx[i] * fr, wi = kx[i] * fi;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(Rre + j, (T)(wr * ky[j]));
-                atomicAdd(Rim + j, (T)(wi * ky[j]));
+                atomicAdd(Rre + j, wr * ky[j]);
+                atomicAdd(Rim + j, wi * ky[j]);
             }
         }
     }
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         const int i = e / SY, j = e - i * SY;
         const int row = r0 + i;
         if (row >= a.rows_used) continue;
-        const T vr = Sre[i * SYP + j], vi = Sim[i * SYP + j];
+        const T vr = (T)Sre[i * SYP + j], vi = (T)Sim[i * SYP + j];
         if (vr == (T)0 && vi == (T)0) continue;
         const int col = (c0 + j) % a.Nphi;  // the subgrid may wrap more than once when Nphi is small
         T *dst = U + 2 * ((int64_t)row * a.Nphi + col);
@@ -189,7 +192,7 @@ template <typename T, int W>
 static hipError_t launch_spread_w(const psht_plan_s &p, const void *map, void *U, hipStream_t st) {
     typedef typename CplxT<T>::type C;
     NufftArgs a = nufft_args(p);
-    size_t lds = (size_t)(p.tile_x + W - 1) * ((p.tile_y + W - 1) | 1) * sizeof(C);
+    size_t lds = (size_t)(p.tile_x + W - 1) * ((p.tile_y + W - 1) | 1) * 2 * sizeof(double);
     hipLaunchKernelGGL((k_spread<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
                        static_cast<const C *>(map), static_cast<T *>(U));
     return hipGetLastError();
@@ -371,8 +374,105 @@ __global__ void k_point_scatter(SortArgs a, const double *theta, const double *p
     perm[pos] = (int32_t)i;
 }
 
+// Order inside a tile.  Points are ranked within their stencil-origin cell
+// (0 for the first point of a cell, 1 for the second, ...) and laid out rank
+// by rank, each rank level in row-major cell order.  Consecutive lanes of a
+// wave then take points of distinct, mostly adjacent cells, so the W x W
+// stencils they update or read in LDS in one instruction hit distinct
+// addresses in distinct banks.  Ranks from kRankLevels - 1 up share the last
+// level (in arbitrary order), which bounds the work for cells holding very
+// many points.
+constexpr int kRankLevels = 16;
+constexpr int kOrderThreads = 256;
+
+__device__ inline int cell_in_tile(const SortArgs &a, double X, double Y, int r0, int c0) {
+    const int a0 = stencil_origin(X, a.W), b0 = stencil_origin(Y, a.W);
+    int b0m = b0 % a.Nphi;
+    if (b0m < 0) b0m += a.Nphi;
+    const int li = min(max(a0 - a.row_lo - r0, 0), a.tile_x - 1);
+    const int lj = min(max(b0m - c0, 0), a.tile_y - 1);
+    return li * a.tile_y + lj;
+}
+
+// Exclusive block scan of v[0..n) in place (kOrderThreads threads, part[] of
+// kOrderThreads ints); returns the total.  Every thread must call it.
+__device__ inline int block_exclusive_scan(int32_t *v, int n, int32_t *part) {
+    const int per = (n + kOrderThreads - 1) / kOrderThreads;
+    const int b = threadIdx.x * per, e = min(n, b + per);
+    int32_t s = 0;
+    for (int i = b; i < e; ++i) s += v[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kOrderThreads; off <<= 1) {
+        const int32_t u = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += u;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+    for (int i = b; i < e; ++i) {
+        const int32_t c = v[i];
+        v[i] = run;
+        run += c;
+    }
+    const int32_t total = part[kOrderThreads - 1];
+    __syncthreads();
+    return total;
+}
+
+// One workgroup per tile: reorders the tile's points from (tpx, tpy, tperm)
+// into (px, py, perm).  rank[] is per-point scratch.
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const int32_t *tile_start,
+                                                              const double *tpx, const double *tpy,
+                                                              const int32_t *tperm, int32_t *rank, double *px,
+                                                              double *py, int32_t *perm) {
+    extern __shared__ int32_t osm[];
+    const int C = a.tile_x * a.tile_y;
+    int32_t *cnt = osm, *pos = osm + C, *part = osm + 2 * C;
+    __shared__ int32_t s_kmax, s_cursor;
+    const int t = blockIdx.x;
+    const int p0 = tile_start[t], p1 = tile_start[t + 1];
+    if (p0 == p1) return;
+    const int r0 = (t / a.nty) * a.tile_x, c0 = (t % a.nty) * a.tile_y;
+    for (int c = threadIdx.x; c < C; c += kOrderThreads) cnt[c] = 0;
+    if (threadIdx.x == 0) {
+        s_kmax = 0;
+        s_cursor = 0;
+    }
+    __syncthreads();
+    for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
+        const int r = atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
+        rank[p] = r;
+        atomicMax(&s_kmax, r + 1);
+    }
+    __syncthreads();
+    const int levels = min(s_kmax, kRankLevels);
+    int base = p0;
+    for (int lev = 0; lev < levels; ++lev) {
+        const bool last = lev == kRankLevels - 1;
+        for (int c = threadIdx.x; c < C; c += kOrderThreads) pos[c] = cnt[c] > lev ? (last ? cnt[c] - lev : 1) : 0;
+        __syncthreads();
+        const int n_lev = block_exclusive_scan(pos, C, part);
+        for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
+            const int r = rank[p];
+            if (r < lev || (r > lev && !last)) continue;
+            const int cell = cell_in_tile(a, tpx[p], tpy[p], r0, c0);
+            const int dst = base + pos[cell] + (last ? r - lev : 0);
+            px[dst] = tpx[p];
+            py[dst] = tpy[p];
+            perm[dst] = tperm[p];
+        }
+        base += n_lev;
+        __syncthreads();
+    }
+}
+
+size_t tile_order_lds_bytes(int tile_x, int tile_y) {
+    return sizeof(int32_t) * (2 * (size_t)tile_x * tile_y + kOrderThreads);
+}
+
 hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
-                             int32_t *d_cursor, hipStream_t st) {
+                             int32_t *d_cursor, double *tpx, double *tpy, int32_t *tperm, hipStream_t st) {
     SortArgs a;
     a.sx = p.g.sx;
     a.sy = p.g.sy;
@@ -396,8 +496,12 @@ hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cursor, p.ntiles, p.d_tile_start, d_cursor);
     if (n > 0) {
         unsigned nb = (unsigned)((n + 255) / 256);
-        hipLaunchKernelGGL(k_point_scatter, dim3(nb), dim3(256), 0, st, a, theta, phi, n, d_keys, d_cursor, p.d_px,
-                           p.d_py, p.d_perm);
+        hipLaunchKernelGGL(k_point_scatter, dim3(nb), dim3(256), 0, st, a, theta, phi, n, d_keys, d_cursor, tpx, tpy,
+                           tperm);
+        // keys are no longer needed: they hold the per-point ranks from here on
+        hipLaunchKernelGGL(k_tile_order, dim3((unsigned)p.ntiles), dim3(kOrderThreads),
+                           tile_order_lds_bytes(p.tile_x, p.tile_y), st, a, p.d_tile_start, tpx, tpy, tperm, d_keys,
+                           p.d_px, p.d_py, p.d_perm);
     }
     return hipGetLastError();
 }

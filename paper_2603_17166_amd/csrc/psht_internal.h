@@ -154,7 +154,7 @@ hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, co
 hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n, double *d_stats,
                               hipStream_t st);
 hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
-                             int32_t *d_cursor, hipStream_t st);
+                             int32_t *d_cursor, double *tpx, double *tpy, int32_t *tperm, hipStream_t st);
 
 // Rings per lane of the Legendre kernels (a work item covers 64 x this many rings).
 int leg_rings_per_lane();
