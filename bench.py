@@ -74,6 +74,36 @@ def cpu_baseline(w, n_sample: int) -> dict:
                       "(synth %.1f s, adjoint %.1f s)" % (idx.shape[0], t1 - t0, t2 - t1)}
 
 
+STAGE_KERNEL = {"leg_synth": "psht::k_leg_synth", "leg_adj": "psht::k_leg_adjoint", "theta_synth": "psht::k_theta_synth",
+                "theta_adj": "psht::k_theta_adjoint", "phi_synth": "psht::k_phi_synth", "phi_adj": "psht::k_phi_adjoint",
+                "interp": "psht::k_interp", "spread": "psht::k_spread"}
+
+
+def measured_traffic(stage: str, workload: str):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE counts (profiles/traffic.json), or None when there
+    are none for this workload or the kernel's sources changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if stage not in STAGE_KERNEL or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh).get(workload, {})
+    for name, e in table.items():
+        if not name.startswith(STAGE_KERNEL[stage] + "<"):
+            continue
+        h = hashlib.sha256()
+        for f in e["sources"]:
+            with open(os.path.join(ROOT, "paper_2603_17166_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != e["source_sha256_16"]:
+            return None
+        return {"bytes": e["fetch_bytes"] + e["write_bytes"], "read_bytes": e["fetch_bytes"],
+                "write_bytes": e["write_bytes"], "kernel": name}
+    return None
+
+
 def stage_avgs(stages: dict) -> dict:
     return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
 
@@ -98,7 +128,11 @@ def roofline(w, info, avg: dict) -> dict:
         roof = {"bound": "hbm", "achieved": nbytes / (avg[dom] * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "work": "%.4g B per launch" % nbytes}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    t = measured_traffic(dom, w.name)
+    roof["traffic"] = t["bytes"] if t else None
+    if t:
+        roof["traffic_detail"] = "HBM bytes per launch of %s: read %.4g, write %.4g (rocprofv3 FETCH_SIZE x2.0, " \
+                                 "WRITE_SIZE x1.0 by a 1 GiB copy)" % (t["kernel"], t["read_bytes"], t["write_bytes"])
     roof["kernel"] = dom
     roof["launch_ms"] = avg[dom]
     return roof

@@ -176,13 +176,27 @@ struct StageArgs {
     const double *psihat_t, *psihat_p;
 };
 
+// Column of the Theta stage handled by block b.  Blocks are dealt to the 8
+// XCDs round-robin; this map gives each XCD one contiguous range of columns,
+// walked in order, so the workgroups resident on an XCD at any time touch
+// neighbouring columns of the row-major V array and share its cache lines in
+// that XCD's L2 (one column alone would use 16 of every 128 bytes it moves).
+// The grid has 8 * ceil(ncol / 8) blocks; blocks past the end return.
+__device__ inline int xcd_column(int b, int ncol) {
+    const int per = (ncol + 7) >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+static inline unsigned xcd_grid(int ncol) { return 8u * (unsigned)((ncol + 7) / 8); }
+
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_theta_synth(StageArgs a, const double2 *F,
                                                              typename CT<T>::type *V) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
-    const int mi = blockIdx.x;
+    const int mi = xcd_column(blockIdx.x, 2 * a.mmax + 1);
+    if (mi > 2 * a.mmax) return;
     const int am = abs(mi - a.mmax);
     const double sig = ((a.spin + am) & 1) ? -1.0 : 1.0;  // mirror sign (-1)^(s+m)
     const int L = a.L, N2 = a.N2, NT = a.NT;
@@ -228,7 +242,8 @@ __global__ __launch_bounds__(kFftThreads) void k_theta_adjoint(StageArgs a, cons
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
-    const int mi = blockIdx.x;
+    const int mi = xcd_column(blockIdx.x, 2 * a.mmax + 1);
+    if (mi > 2 * a.mmax) return;
     const int am = abs(mi - a.mmax);
     const double sig = ((a.spin + am) & 1) ? -1.0 : 1.0;
     const int L = a.L, N2 = a.N2, NT = a.NT;
@@ -366,7 +381,7 @@ template <typename F> static hipError_t set_lds(F kern, size_t bytes) {
 
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st) {
     StageArgs a = stage_args(p);
-    dim3 grid(2 * p.g.mmax + 1), block(kFftThreads);
+    dim3 grid(xcd_grid(2 * p.g.mmax + 1)), block(kFftThreads);
     const double2 *F2 = reinterpret_cast<const double2 *>(F);
     if (p.g.fp32) {
         size_t lds = (size_t)p.g.Ntheta * sizeof(float2);
@@ -382,7 +397,7 @@ hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hi
 
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st) {
     StageArgs a = stage_args(p);
-    dim3 grid(2 * p.g.mmax + 1), block(kFftThreads);
+    dim3 grid(xcd_grid(2 * p.g.mmax + 1)), block(kFftThreads);
     double2 *F2 = reinterpret_cast<double2 *>(F);
     if (p.g.fp32) {
         size_t lds = (size_t)p.g.Ntheta * sizeof(float2);
