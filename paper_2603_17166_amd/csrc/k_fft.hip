@@ -17,6 +17,8 @@
 // The FFT is a mixed-radix (4, 2, 3, 5, 7, 11, 13) Stockham transform held in
 // LDS: each pass stages its butterfly inputs in registers, synchronises, and
 // writes the outputs in place, so one buffer of n complex values suffices.
+#include <type_traits>
+
 #include "psht_internal.h"
 
 namespace psht {
@@ -48,11 +50,6 @@ static FftDev to_dev(const FftFactors &f) {
     return d;
 }
 
-constexpr int kFftThreads = 512;
-
-template <typename T> struct FftLimit;
-template <> struct FftLimit<double> { static constexpr int value = kFftMaxLds64; };
-template <> struct FftLimit<float> { static constexpr int value = kFftMaxLds32; };
 
 // e^{sign 2 pi i t / n} from the table tw[k] = e^{-2 pi i k / n}.
 template <typename C> __device__ inline C twiddle(const double2 *tw, int k, int sign) {
@@ -63,13 +60,40 @@ template <typename C> __device__ inline C twiddle(const double2 *tw, int k, int 
     return r;
 }
 
-// Radix-R DFT in registers: y_q = sum_r v_r e^{sign 2 pi i r q / R}.
-template <typename C, int R> __device__ inline void dft(C *v, const C *wr, int sign) {
-    if (R == 2) {
+// cos and sin of 2 pi k / R for the odd radices.
+template <int R> struct Rot;
+template <> struct Rot<3> {
+    static constexpr double c[3] = {1, -0.49999999999999978, -0.50000000000000044};
+    static constexpr double s[3] = {0, 0.86602540378443871, -0.86602540378443837};
+};
+template <> struct Rot<5> {
+    static constexpr double c[5] = {1, 0.30901699437494745, -0.80901699437494734, -0.80901699437494756, 0.30901699437494723};
+    static constexpr double s[5] = {0, 0.95105651629515353, 0.58778525229247325, -0.58778525229247303, -0.95105651629515364};
+};
+template <> struct Rot<7> {
+    static constexpr double c[7] = {1, 0.62348980185873359, -0.22252093395631434, -0.90096886790241903, -0.90096886790241915, -0.22252093395631459, 0.62348980185873337};
+    static constexpr double s[7] = {0, 0.7818314824680298, 0.97492791218182362, 0.43388373911755823, -0.43388373911755801, -0.97492791218182362, -0.78183148246802991};
+};
+template <> struct Rot<11> {
+    static constexpr double c[11] = {1, 0.84125353283118121, 0.41541501300188644, -0.142314838273285, -0.65486073394528499, -0.95949297361449737, -0.95949297361449748, -0.65486073394528521, -0.14231483827328523, 0.41541501300188605, 0.84125353283118121};
+    static constexpr double s[11] = {0, 0.54064081745559756, 0.90963199535451833, 0.9898214418809328, 0.75574957435425827, 0.28173255684142967, -0.28173255684142939, -0.75574957435425816, -0.98982144188093268, -0.90963199535451855, -0.54064081745559744};
+};
+template <> struct Rot<13> {
+    static constexpr double c[13] = {1, 0.88545602565320991, 0.56806474673115592, 0.12053668025532301, -0.35460488704253545, -0.74851074817110119, -0.97094181742605201, -0.97094181742605212, -0.7485107481711013, -0.3546048870425359, 0.1205366802553232, 0.56806474673115481, 0.88545602565321002};
+    static constexpr double s[13] = {0, 0.46472317204376851, 0.82298386589365635, 0.99270887409805397, 0.93501624268541483, 0.66312265824079519, 0.23931566428755768, -0.23931566428755743, -0.66312265824079497, -0.93501624268541472, -0.99270887409805397, -0.82298386589365702, -0.4647231720437684};
+};
+
+// Radix-R DFT in registers: y_q = sum_r v_r e^{sign 2 pi i r q / R}.  Odd R
+// uses the symmetric form: with t_r = v_r + v_{R-r} and u_r = v_r - v_{R-r},
+// y_q = a_q + sign i b_q and y_{R-q} = a_q - sign i b_q, where
+// a_q = v_0 + sum_r t_r cos(2 pi r q / R), b_q = sum_r u_r sin(2 pi r q / R),
+// r, q = 1..(R-1)/2, with compile-time constants.
+template <typename C, int R> __device__ inline void dft(C *v, int sign) {
+    if constexpr (R == 2) {
         C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
-    } else if (R == 4) {
+    } else if constexpr (R == 4) {
         C a = cadd(v[0], v[2]), b = csub(v[0], v[2]), c = cadd(v[1], v[3]), d0 = csub(v[1], v[3]);
         C d;  // (sign i) * d0
         d.x = -sign * d0.y;
@@ -79,33 +103,56 @@ template <typename C, int R> __device__ inline void dft(C *v, const C *wr, int s
         v[1] = cadd(b, d);
         v[3] = csub(b, d);
     } else {
-        C out[R];
+        typedef decltype(v[0].x) S;
+        constexpr int H = (R - 1) / 2;
+        C t[H + 1], u[H + 1];
+        C y0 = v[0];
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            C acc = v[0];
-#pragma unroll
-            for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], wr[(r * q) % R]));
-            out[q] = acc;
+        for (int r = 1; r <= H; ++r) {
+            t[r] = cadd(v[r], v[R - r]);
+            u[r] = csub(v[r], v[R - r]);
+            y0 = cadd(y0, t[r]);
         }
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = out[q];
+        for (int q = 1; q <= H; ++q) {
+            C a = v[0], b;
+            b.x = b.y = (S)0;
+#pragma unroll
+            for (int r = 1; r <= H; ++r) {
+                const S cr = (S)Rot<R>::c[(r * q) % R], sr = (S)Rot<R>::s[(r * q) % R];
+                a.x += t[r].x * cr;
+                a.y += t[r].y * cr;
+                b.x += u[r].x * sr;
+                b.y += u[r].y * sr;
+            }
+            // sign i b = (-sign b.y, sign b.x)
+            v[q].x = a.x - sign * b.y;
+            v[q].y = a.y + sign * b.x;
+            v[R - q].x = a.x + sign * b.y;
+            v[R - q].y = a.y - sign * b.x;
+        }
+        v[0] = y0;
     }
 }
 
-// One Stockham pass of radix R on buf[0..n) with stride Ns.
-template <typename T, int R>
+// Threads of a workgroup transforming up to MAXN points.
+__host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2048 ? 256 : 512; }
+
+// One Stockham pass of radix R on buf[0..n) with stride Ns.  Every thread
+// holds NB butterflies in registers; NB follows from the largest transform
+// length MAXN the kernel is built for, so short transforms do not pay the
+// registers of long ones.
+template <typename T, int R, int MAXN>
 __device__ void fft_pass(typename CT<T>::type *buf, int n, int Ns, int sign, const double2 *tw) {
     typedef typename CT<T>::type C;
-    constexpr int NB = (FftLimit<T>::value / R + kFftThreads - 1) / kFftThreads;
+    constexpr int NT = fft_threads(MAXN);
+    constexpr int NB = (MAXN / R + NT - 1) / NT;
     const int nb = n / R;
     const int tws = n / (Ns * R);
-    C wr[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) wr[t] = twiddle<C>(tw, t * (n / R), sign);
     C v[NB][R];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        int b = threadIdx.x + i * kFftThreads;
+        int b = threadIdx.x + i * NT;
         if (b < nb) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * nb];
@@ -114,12 +161,12 @@ __device__ void fft_pass(typename CT<T>::type *buf, int n, int Ns, int sign, con
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        int b = threadIdx.x + i * kFftThreads;
+        int b = threadIdx.x + i * NT;
         if (b < nb) {
             int k = b % Ns;
 #pragma unroll
             for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twiddle<C>(tw, r * k * tws, sign));
-            dft<C, R>(v[i], wr, sign);
+            dft<C, R>(v[i], sign);
             int d = (b - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[d + r * Ns] = v[i][r];
@@ -128,20 +175,20 @@ __device__ void fft_pass(typename CT<T>::type *buf, int n, int Ns, int sign, con
     __syncthreads();
 }
 
-// In-place FFT of buf[0..n) in LDS; the caller synchronises before the call.
-template <typename T>
+// In-place FFT of buf[0..n) in LDS, n <= MAXN; the caller synchronises before the call.
+template <typename T, int MAXN>
 __device__ void lds_fft(typename CT<T>::type *buf, const FftDev &f, int sign, const double2 *tw) {
     int Ns = 1;
     for (int p = 0; p < f.npass; ++p) {
         const int R = f.radix[p];
         switch (R) {
-            case 4: fft_pass<T, 4>(buf, f.n, Ns, sign, tw); break;
-            case 2: fft_pass<T, 2>(buf, f.n, Ns, sign, tw); break;
-            case 3: fft_pass<T, 3>(buf, f.n, Ns, sign, tw); break;
-            case 5: fft_pass<T, 5>(buf, f.n, Ns, sign, tw); break;
-            case 7: fft_pass<T, 7>(buf, f.n, Ns, sign, tw); break;
-            case 11: fft_pass<T, 11>(buf, f.n, Ns, sign, tw); break;
-            case 13: fft_pass<T, 13>(buf, f.n, Ns, sign, tw); break;
+            case 4: fft_pass<T, 4, MAXN>(buf, f.n, Ns, sign, tw); break;
+            case 2: fft_pass<T, 2, MAXN>(buf, f.n, Ns, sign, tw); break;
+            case 3: fft_pass<T, 3, MAXN>(buf, f.n, Ns, sign, tw); break;
+            case 5: fft_pass<T, 5, MAXN>(buf, f.n, Ns, sign, tw); break;
+            case 7: fft_pass<T, 7, MAXN>(buf, f.n, Ns, sign, tw); break;
+            case 11: fft_pass<T, 11, MAXN>(buf, f.n, Ns, sign, tw); break;
+            case 13: fft_pass<T, 13, MAXN>(buf, f.n, Ns, sign, tw); break;
             default: break;
         }
         Ns *= R;
@@ -150,18 +197,18 @@ __device__ void lds_fft(typename CT<T>::type *buf, const FftDev &f, int sign, co
 
 // ------------------------------------------------------------ plain rows
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_rows(FftDev f, int sign, const double2 *tw,
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads(MAXN)) void k_fft_rows(FftDev f, int sign, const double2 *tw,
                                                           const typename CT<T>::type *in,
                                                           typename CT<T>::type *out) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
     const int64_t row = blockIdx.x;
-    for (int k = threadIdx.x; k < f.n; k += kFftThreads) buf[k] = in[row * f.n + k];
+    for (int k = threadIdx.x; k < f.n; k += fft_threads(MAXN)) buf[k] = in[row * f.n + k];
     __syncthreads();
-    lds_fft<T>(buf, f, sign, tw);
-    for (int k = threadIdx.x; k < f.n; k += kFftThreads) out[row * f.n + k] = buf[k];
+    lds_fft<T, MAXN>(buf, f, sign, tw);
+    for (int k = threadIdx.x; k < f.n; k += fft_threads(MAXN)) out[row * f.n + k] = buf[k];
 }
 
 // ------------------------------------------------------------ Theta stage
@@ -189,8 +236,8 @@ __device__ inline int xcd_column(int b, int ncol) {
 
 static inline unsigned xcd_grid(int ncol) { return 8u * (unsigned)((ncol + 7) / 8); }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_theta_synth(StageArgs a, const double2 *F,
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_synth(StageArgs a, const double2 *F,
                                                              typename CT<T>::type *V) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -201,7 +248,7 @@ __global__ __launch_bounds__(kFftThreads) void k_theta_synth(StageArgs a, const 
     const double sig = ((a.spin + am) & 1) ? -1.0 : 1.0;  // mirror sign (-1)^(s+m)
     const int L = a.L, N2 = a.N2, NT = a.NT;
     const double2 *Fm = F + (int64_t)mi * a.nring;
-    for (int k = threadIdx.x; k < N2; k += kFftThreads) {
+    for (int k = threadIdx.x; k < N2; k += fft_threads(MAXN)) {
         const int j = k <= L ? k : N2 - k;
         const double wj = (k <= L ? 1.0 : sig) * a.ring_w[j];
         double2 v = make_double2(0.0, 0.0);
@@ -212,12 +259,12 @@ __global__ __launch_bounds__(kFftThreads) void k_theta_synth(StageArgs a, const 
         buf[k] = c;
     }
     __syncthreads();
-    lds_fft<T>(buf, a.fn2, -1, a.tw_n2);  // N2 * Fourier coefficient
+    lds_fft<T, MAXN>(buf, a.fn2, -1, a.tw_n2);  // N2 * Fourier coefficient
     // divide by N2 psihat(|n|) and pad to NT: n < 0 moves from N2 - |n| to NT - |n|
-    for (int n = 1 + threadIdx.x; n <= L; n += kFftThreads)
+    for (int n = 1 + threadIdx.x; n <= L; n += fft_threads(MAXN))
         buf[NT - n] = cscale(buf[N2 - n], (T)(1.0 / (N2 * a.psihat_t[n])));
     __syncthreads();
-    for (int k = threadIdx.x; k < NT - L; k += kFftThreads) {
+    for (int k = threadIdx.x; k < NT - L; k += fft_threads(MAXN)) {
         if (k <= L) {
             buf[k] = cscale(buf[k], (T)(1.0 / (N2 * a.psihat_t[k])));
         } else {
@@ -227,17 +274,17 @@ __global__ __launch_bounds__(kFftThreads) void k_theta_synth(StageArgs a, const 
         }
     }
     __syncthreads();
-    lds_fft<T>(buf, a.fnt, +1, a.tw_nt);
+    lds_fft<T, MAXN>(buf, a.fnt, +1, a.tw_nt);
     const int64_t ldv = 2 * a.mmax + 1;
-    for (int r = threadIdx.x; r < a.rows_used; r += kFftThreads) {
+    for (int r = threadIdx.x; r < a.rows_used; r += fft_threads(MAXN)) {
         int row = (a.row_lo + r) % NT;
         if (row < 0) row += NT;
         V[(int64_t)r * ldv + mi] = buf[row];
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_theta_adjoint(StageArgs a, const typename CT<T>::type *V,
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_adjoint(StageArgs a, const typename CT<T>::type *V,
                                                                double2 *F) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -250,25 +297,25 @@ __global__ __launch_bounds__(kFftThreads) void k_theta_adjoint(StageArgs a, cons
     const int64_t ldv = 2 * a.mmax + 1;
     C z;
     z.x = z.y = (T)0;
-    for (int k = threadIdx.x; k < NT; k += kFftThreads) buf[k] = z;
+    for (int k = threadIdx.x; k < NT; k += fft_threads(MAXN)) buf[k] = z;
     __syncthreads();
-    for (int r = threadIdx.x; r < a.rows_used; r += kFftThreads) {
+    for (int r = threadIdx.x; r < a.rows_used; r += fft_threads(MAXN)) {
         int row = (a.row_lo + r) % NT;
         if (row < 0) row += NT;
         buf[row] = V[(int64_t)r * ldv + mi];
     }
     __syncthreads();
-    lds_fft<T>(buf, a.fnt, -1, a.tw_nt);
+    lds_fft<T, MAXN>(buf, a.fnt, -1, a.tw_nt);
     // keep |n| <= L, divide by N2 psihat, move n < 0 from NT - |n| to N2 - |n|
-    for (int k = threadIdx.x; k <= L; k += kFftThreads) {
+    for (int k = threadIdx.x; k <= L; k += fft_threads(MAXN)) {
         const T sc = (T)(1.0 / (N2 * a.psihat_t[k]));
         buf[k] = cscale(buf[k], sc);
         if (k >= 1) buf[N2 - k] = cscale(buf[NT - k], sc);
     }
     __syncthreads();
-    lds_fft<T>(buf, a.fn2, +1, a.tw_n2);
+    lds_fft<T, MAXN>(buf, a.fn2, +1, a.tw_n2);
     double2 *Fm = F + (int64_t)mi * a.nring;
-    for (int j = threadIdx.x; j <= L; j += kFftThreads) {
+    for (int j = threadIdx.x; j <= L; j += fft_threads(MAXN)) {
         C v = buf[j];
         double re = v.x, im = v.y;
         if (j > 0) {
@@ -283,8 +330,8 @@ __global__ __launch_bounds__(kFftThreads) void k_theta_adjoint(StageArgs a, cons
 
 // -------------------------------------------------------------- phi stage
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_phi_synth(StageArgs a, const typename CT<T>::type *V,
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_synth(StageArgs a, const typename CT<T>::type *V,
                                                            typename CT<T>::type *U) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -296,27 +343,27 @@ __global__ __launch_bounds__(kFftThreads) void k_phi_synth(StageArgs a, const ty
     C z;
     z.x = z.y = (T)0;
     for (int h = 0; h < (a.split ? 2 : 1); ++h) {
-        for (int k = threadIdx.x; k < nh; k += kFftThreads) buf[k] = z;
+        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = z;
         __syncthreads();
-        for (int mi = threadIdx.x; mi <= 2 * mm; mi += kFftThreads) {
+        for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads(MAXN)) {
             const int m = mi - mm;
             C v = cscale(Vr[mi], (T)(1.0 / a.psihat_p[abs(m)]));
             if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, +1));
             buf[m < 0 ? m + nh : m] = v;
         }
         __syncthreads();
-        lds_fft<T>(buf, a.fnp, +1, a.tw_np);
+        lds_fft<T, MAXN>(buf, a.fnp, +1, a.tw_np);
         if (a.split) {
-            for (int k = threadIdx.x; k < nh; k += kFftThreads) Ur[2 * k + h] = buf[k];
+            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[2 * k + h] = buf[k];
         } else {
-            for (int k = threadIdx.x; k < nh; k += kFftThreads) Ur[k] = buf[k];
+            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[k] = buf[k];
         }
         __syncthreads();
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_phi_adjoint(StageArgs a, const typename CT<T>::type *U,
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_adjoint(StageArgs a, const typename CT<T>::type *U,
                                                              typename CT<T>::type *V) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -327,13 +374,13 @@ __global__ __launch_bounds__(kFftThreads) void k_phi_adjoint(StageArgs a, const 
     const C *Ur = U + r * Np;
     for (int h = 0; h < (a.split ? 2 : 1); ++h) {
         if (a.split) {
-            for (int k = threadIdx.x; k < nh; k += kFftThreads) buf[k] = Ur[2 * k + h];
+            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = Ur[2 * k + h];
         } else {
-            for (int k = threadIdx.x; k < nh; k += kFftThreads) buf[k] = Ur[k];
+            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = Ur[k];
         }
         __syncthreads();
-        lds_fft<T>(buf, a.fnp, -1, a.tw_np);
-        for (int mi = threadIdx.x; mi <= 2 * mm; mi += kFftThreads) {
+        lds_fft<T, MAXN>(buf, a.fnp, -1, a.tw_np);
+        for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads(MAXN)) {
             const int m = mi - mm;
             C v = buf[m < 0 ? m + nh : m];
             if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, -1));
@@ -379,91 +426,114 @@ template <typename F> static hipError_t set_lds(F kern, size_t bytes) {
                                (int)bytes);
 }
 
+// Calls fn(std::integral_constant<int, MAXN>) for the smallest build size
+// MAXN >= n (n <= 8192).
+template <typename Fn> static void tier_dispatch(int n, Fn fn) {
+    if (n <= 1024) fn(std::integral_constant<int, 1024>());
+    else if (n <= 2048) fn(std::integral_constant<int, 2048>());
+    else if (n <= 4096) fn(std::integral_constant<int, 4096>());
+    else fn(std::integral_constant<int, 8192>());
+}
+
+template <typename T>
+static void theta_synth_t(const psht_plan_s &p, const StageArgs &a, const double2 *F, void *V, hipStream_t st) {
+    typedef typename CT<T>::type C;
+    const size_t lds = (size_t)p.g.Ntheta * sizeof(C);
+    tier_dispatch(p.g.Ntheta, [&](auto M) {
+        constexpr int MX = decltype(M)::value;
+        set_lds(k_theta_synth<T, MX>, lds);
+        hipLaunchKernelGGL((k_theta_synth<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads(MX)), lds, st,
+                           a, F, static_cast<C *>(V));
+    });
+}
+
+template <typename T>
+static void theta_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *V, double2 *F, hipStream_t st) {
+    typedef typename CT<T>::type C;
+    const size_t lds = (size_t)p.g.Ntheta * sizeof(C);
+    tier_dispatch(p.g.Ntheta, [&](auto M) {
+        constexpr int MX = decltype(M)::value;
+        set_lds(k_theta_adjoint<T, MX>, lds);
+        hipLaunchKernelGGL((k_theta_adjoint<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads(MX)), lds,
+                           st, a, static_cast<const C *>(V), F);
+    });
+}
+
+template <typename T>
+static void phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V, void *U, hipStream_t st) {
+    typedef typename CT<T>::type C;
+    const int nh = p.phi_split ? p.g.Nphi / 2 : p.g.Nphi;
+    const size_t lds = (size_t)nh * sizeof(C);
+    tier_dispatch(nh, [&](auto M) {
+        constexpr int MX = decltype(M)::value;
+        set_lds(k_phi_synth<T, MX>, lds);
+        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(p.g.rows_used), dim3(fft_threads(MX)), lds, st, a,
+                           static_cast<const C *>(V), static_cast<C *>(U));
+    });
+}
+
+template <typename T>
+static void phi_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *U, void *V, hipStream_t st) {
+    typedef typename CT<T>::type C;
+    const int nh = p.phi_split ? p.g.Nphi / 2 : p.g.Nphi;
+    const size_t lds = (size_t)nh * sizeof(C);
+    tier_dispatch(nh, [&](auto M) {
+        constexpr int MX = decltype(M)::value;
+        set_lds(k_phi_adjoint<T, MX>, lds);
+        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(p.g.rows_used), dim3(fft_threads(MX)), lds, st, a,
+                           static_cast<const C *>(U), static_cast<C *>(V));
+    });
+}
+
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st) {
-    StageArgs a = stage_args(p);
-    dim3 grid(xcd_grid(2 * p.g.mmax + 1)), block(kFftThreads);
+    const StageArgs a = stage_args(p);
     const double2 *F2 = reinterpret_cast<const double2 *>(F);
-    if (p.g.fp32) {
-        size_t lds = (size_t)p.g.Ntheta * sizeof(float2);
-        set_lds(k_theta_synth<float>, lds);
-        hipLaunchKernelGGL(k_theta_synth<float>, grid, block, lds, st, a, F2, static_cast<float2 *>(V));
-    } else {
-        size_t lds = (size_t)p.g.Ntheta * sizeof(double2);
-        set_lds(k_theta_synth<double>, lds);
-        hipLaunchKernelGGL(k_theta_synth<double>, grid, block, lds, st, a, F2, static_cast<double2 *>(V));
-    }
+    if (p.g.fp32) theta_synth_t<float>(p, a, F2, V, st);
+    else theta_synth_t<double>(p, a, F2, V, st);
     return hipGetLastError();
 }
 
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st) {
-    StageArgs a = stage_args(p);
-    dim3 grid(xcd_grid(2 * p.g.mmax + 1)), block(kFftThreads);
+    const StageArgs a = stage_args(p);
     double2 *F2 = reinterpret_cast<double2 *>(F);
-    if (p.g.fp32) {
-        size_t lds = (size_t)p.g.Ntheta * sizeof(float2);
-        set_lds(k_theta_adjoint<float>, lds);
-        hipLaunchKernelGGL(k_theta_adjoint<float>, grid, block, lds, st, a, static_cast<const float2 *>(V), F2);
-    } else {
-        size_t lds = (size_t)p.g.Ntheta * sizeof(double2);
-        set_lds(k_theta_adjoint<double>, lds);
-        hipLaunchKernelGGL(k_theta_adjoint<double>, grid, block, lds, st, a, static_cast<const double2 *>(V), F2);
-    }
+    if (p.g.fp32) theta_adjoint_t<float>(p, a, V, F2, st);
+    else theta_adjoint_t<double>(p, a, V, F2, st);
     return hipGetLastError();
 }
 
 hipError_t launch_phi_synth(const psht_plan_s &p, const void *V, void *U, hipStream_t st) {
-    StageArgs a = stage_args(p);
-    dim3 grid(p.g.rows_used), block(kFftThreads);
-    int nh = p.phi_split ? p.g.Nphi / 2 : p.g.Nphi;
-    if (p.g.fp32) {
-        size_t lds = (size_t)nh * sizeof(float2);
-        set_lds(k_phi_synth<float>, lds);
-        hipLaunchKernelGGL(k_phi_synth<float>, grid, block, lds, st, a, static_cast<const float2 *>(V),
-                           static_cast<float2 *>(U));
-    } else {
-        size_t lds = (size_t)nh * sizeof(double2);
-        set_lds(k_phi_synth<double>, lds);
-        hipLaunchKernelGGL(k_phi_synth<double>, grid, block, lds, st, a, static_cast<const double2 *>(V),
-                           static_cast<double2 *>(U));
-    }
+    const StageArgs a = stage_args(p);
+    if (p.g.fp32) phi_synth_t<float>(p, a, V, U, st);
+    else phi_synth_t<double>(p, a, V, U, st);
     return hipGetLastError();
 }
 
 hipError_t launch_phi_adjoint(const psht_plan_s &p, const void *U, void *V, hipStream_t st) {
-    StageArgs a = stage_args(p);
-    dim3 grid(p.g.rows_used), block(kFftThreads);
-    int nh = p.phi_split ? p.g.Nphi / 2 : p.g.Nphi;
-    if (p.g.fp32) {
-        size_t lds = (size_t)nh * sizeof(float2);
-        set_lds(k_phi_adjoint<float>, lds);
-        hipLaunchKernelGGL(k_phi_adjoint<float>, grid, block, lds, st, a, static_cast<const float2 *>(U),
-                           static_cast<float2 *>(V));
-    } else {
-        size_t lds = (size_t)nh * sizeof(double2);
-        set_lds(k_phi_adjoint<double>, lds);
-        hipLaunchKernelGGL(k_phi_adjoint<double>, grid, block, lds, st, a, static_cast<const double2 *>(U),
-                           static_cast<double2 *>(V));
-    }
+    const StageArgs a = stage_args(p);
+    if (p.g.fp32) phi_adjoint_t<float>(p, a, U, V, st);
+    else phi_adjoint_t<double>(p, a, U, V, st);
     return hipGetLastError();
+}
+
+template <typename T>
+static void fft_rows_t(const FftTable &t, int batch, int sign, const void *in, void *out, hipStream_t st) {
+    typedef typename CT<T>::type C;
+    const FftDev f = to_dev(t.f);
+    const double2 *tw = reinterpret_cast<const double2 *>(t.d_tw);
+    const size_t lds = (size_t)t.n * sizeof(C);
+    tier_dispatch(t.n, [&](auto M) {
+        constexpr int MX = decltype(M)::value;
+        set_lds(k_fft_rows<T, MX>, lds);
+        hipLaunchKernelGGL((k_fft_rows<T, MX>), dim3(batch), dim3(fft_threads(MX)), lds, st, f, sign, tw,
+                           static_cast<const C *>(in), static_cast<C *>(out));
+    });
 }
 
 hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, const void *in, void *out,
                            hipStream_t st) {
-    FftDev f = to_dev(t.f);
-    const double2 *tw = reinterpret_cast<const double2 *>(t.d_tw);
-    dim3 grid(batch), block(kFftThreads);
     if (batch == 0) return hipSuccess;
-    if (fp32) {
-        size_t lds = (size_t)t.n * sizeof(float2);
-        set_lds(k_fft_rows<float>, lds);
-        hipLaunchKernelGGL(k_fft_rows<float>, grid, block, lds, st, f, sign, tw, static_cast<const float2 *>(in),
-                           static_cast<float2 *>(out));
-    } else {
-        size_t lds = (size_t)t.n * sizeof(double2);
-        set_lds(k_fft_rows<double>, lds);
-        hipLaunchKernelGGL(k_fft_rows<double>, grid, block, lds, st, f, sign, tw, static_cast<const double2 *>(in),
-                           static_cast<double2 *>(out));
-    }
+    if (fp32) fft_rows_t<float>(t, batch, sign, in, out, st);
+    else fft_rows_t<double>(t, batch, sign, in, out, st);
     return hipGetLastError();
 }
 
