@@ -196,6 +196,39 @@ def run_transform(w, steps: int, warmup: int, check_points: int, log) -> dict:
     return res
 
 
+def batched_maps(w, nmaps: int, steps: int, check_points: int, log) -> dict:
+    """nmaps coefficient sets / maps per call on one plan (the Legendre
+    synthesis runs as one MFMA pass per group of up to 8 maps)."""
+    import torch
+
+    import oracle
+    from paper_2603_17166_amd.plan import Plan
+
+    plan = Plan(w.theta, w.phi, w.lmax, w.spin, w.epsilon, w.precision)
+    alms = [w.alm()] + [syn.gaussian_alm(w.lmax, w.spin, syn.SEED_ALM + 100 + i) for i in range(nmaps - 1)]
+    a = torch.stack([torch.as_tensor(x, device="cuda") for x in alms])
+    f = torch.stack([torch.as_tensor(w.adjoint_map(np.complex64 if plan.info["map_is_fp32"] else np.complex128),
+                                     device="cuda")] * nmaps)
+    out_map = torch.empty((nmaps, w.npoints), dtype=plan.map_dtype, device="cuda")
+    out_alm = torch.empty_like(a)
+    plan.workspace(nmaps)
+    time_steps(plan, a, f, out_map, out_alm, 1, "both")
+    plan.set_timing(True)
+    t_both = time_steps(plan, a, f, out_map, out_alm, steps, "both")
+    avg = stage_avgs(plan.timing())
+    plan.set_timing(False)
+    idx = w.subsample(check_points)
+    ref = oracle.synth(alms[-1], w.theta[idx], w.phi[idx], w.lmax, w.spin)
+    err = float(np.linalg.norm(out_map[-1].cpu().numpy()[idx] - ref) / np.linalg.norm(ref))
+    plan.close()
+    ms = t_both * 1e3 / steps
+    res = {"nmaps": nmaps, "ms_per_step": ms, "points_per_s": nmaps * w.npoints / (ms * 1e-3),
+           "leg_synth_ms_per_map": avg["leg_synth"] / nmaps, "rel_err_vs_oracle_last_map": err,
+           "stage_ms_per_launch": {k: round(v, 4) for k, v in avg.items()}}
+    log("batched %d maps: %.3f ms per step (synth + adjoint of all maps), rel err %.2e" % (nmaps, ms, err))
+    return res
+
+
 def precision_form(steps: int, check_points: int, log) -> dict:
     """FP32 (eps 1e-5) vs FP64 (eps 1e-10) on the 1501 deg^2, lmax 4096 patch."""
     out = {}
@@ -336,6 +369,8 @@ def main() -> int:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
         log("cpu baseline: %.1f points/s" % line["cpu_baseline"]["value"])
     if not args.no_extras:
+        line["batched_maps"] = batched_maps(w, 8, max(3, args.steps // 4), 16, log)
+        line["batched_maps"]["speedup_per_map"] = line["batched_maps"]["points_per_s"] / line["value"]
         line["precision_form"] = precision_form(max(3, args.steps // 4), 32, log)
         line["served"] = served(args.serve_requests, args.serve_load, log)
         line["served_vs_fp64_single"] = line["served"]["points_per_s"] / line["value"]

@@ -199,33 +199,42 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         !upload(p, p.d_ring_w, g.ring_w, st) || !upload(p, p.d_ring_mmax, g.ring_mmax, st))
         return fail(PSHT_ERR_NOMEM, "uploading ring tables");
 
-    // Legendre work items: `group` chunks of 64 R rings per order m, groups padded to a multiple of 8.
+    // Legendre work items: `group` chunks of `chunk` rings per order m, groups
+    // padded to a multiple of 8.  One list for the per-map kernels (64 R rings
+    // per wave) and one of 64-ring chunks for the batched-maps kernel.
     {
-        const int chunk = 64 * psht::leg_rings_per_lane();
-        const int group = (g.nring + chunk - 1) / chunk;
-        int ngroups = ((g.mmax + 1) + 7) / 8 * 8;
-        std::vector<psht::LegItem> items((size_t)ngroups * group, psht::LegItem{0, 0, 0, 0});
-        for (int m = 0; m <= g.mmax; ++m) {
-            int first = -1, last = -1;
-            for (int j = 0; j < g.nring; ++j)
-                if (g.ring_mmax[j] >= m) {
-                    if (first < 0) first = j;
-                    last = j;
-                }
-            for (int c = 0; c < group; ++c) {
-                psht::LegItem &it = items[(size_t)m * group + c];
-                it.m = m;
-                if (first < 0) continue;
-                int jb = first + c * chunk, je = std::min(first + (c + 1) * chunk, last + 1);
-                if (jb < je) {
-                    it.jb = jb;
-                    it.je = je;
+        auto build_items = [&](int chunk, std::vector<psht::LegItem> &items) {
+            const int group = (g.nring + chunk - 1) / chunk;
+            const int ngroups = ((g.mmax + 1) + 7) / 8 * 8;
+            items.assign((size_t)ngroups * group, psht::LegItem{0, 0, 0, 0});
+            for (int m = 0; m <= g.mmax; ++m) {
+                int first = -1, last = -1;
+                for (int j = 0; j < g.nring; ++j)
+                    if (g.ring_mmax[j] >= m) {
+                        if (first < 0) first = j;
+                        last = j;
+                    }
+                for (int c = 0; c < group; ++c) {
+                    psht::LegItem &it = items[(size_t)m * group + c];
+                    it.m = m;
+                    if (first < 0) continue;
+                    int jb = first + c * chunk, je = std::min(first + (c + 1) * chunk, last + 1);
+                    if (jb < je) {
+                        it.jb = jb;
+                        it.je = je;
+                    }
                 }
             }
-        }
+        };
+        std::vector<psht::LegItem> items;
+        const int chunk = 64 * psht::leg_rings_per_lane();
+        build_items(chunk, items);
         p.n_leg_items = (int)items.size();
         p.leg_rings_per_item = chunk;
         if (!upload(p, p.d_leg_items, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
+        build_items(64, items);
+        p.n_leg_items64 = (int)items.size();
+        if (!upload(p, p.d_leg_items64, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
     }
 
     // NUFFT tables
@@ -278,6 +287,17 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     return PSHT_OK;
 }
 
+// Smallest number of maps that takes the batched Legendre pass (PSHT_MM_MIN
+// overrides it for tuning runs; a value above 8 disables the batched pass).
+int leg_batch_min() {
+    static int v = [] {
+        const char *e = getenv("PSHT_MM_MIN");
+        const int x = e ? atoi(e) : 4;
+        return x >= 2 ? x : 4;
+    }();
+    return v;
+}
+
 bool check_ws(const psht_plan_s &p, int nmaps, void *ws, size_t ws_bytes) {
     if (nmaps == 0) return true;
     return ws != nullptr && ws_bytes >= (size_t)nmaps * p.ws_per_map;
@@ -322,20 +342,36 @@ psht_status synth_impl(psht_plan plan, int nmaps, const void *alm, void *map, vo
     const psht::Geometry &g = plan->g;
     const size_t alm_bytes = (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16;
     const size_t map_bytes = (size_t)plan->npts * (g.fp32 ? 8 : 16);
-    for (int i = 0; i < nmaps; ++i) {
-        char *ws = static_cast<char *>(workspace) + (size_t)i * plan->ws_per_map;
-        double *F = reinterpret_cast<double *>(ws);
-        void *V = ws + plan->ws_F;
-        void *U = ws + plan->ws_F + plan->ws_V;
-        void *Q = ws + plan->ws_F + plan->ws_V + plan->ws_U;
-        const void *a = static_cast<const char *>(alm) + i * alm_bytes;
-        void *m = static_cast<char *>(map) + i * map_bytes;
-        psht_plan_s &P = *plan;
-        hipError_t e = timed(P, PSHT_T_LEG_SYNTH, st, [&] { return psht::launch_leg_synth(P, a, F, Q, mscale, st); });
-        if (e == hipSuccess) e = timed(P, PSHT_T_THETA_SYNTH, st, [&] { return psht::launch_theta_synth(P, F, V, st); });
-        if (e == hipSuccess) e = timed(P, PSHT_T_PHI_SYNTH, st, [&] { return psht::launch_phi_synth(P, V, U, st); });
-        if (e == hipSuccess) e = timed(P, PSHT_T_INTERP, st, [&] { return psht::launch_interp(P, U, m, st); });
+    psht_plan_s &P = *plan;
+    const int batch_min = leg_batch_min();
+    for (int i = 0; i < nmaps;) {
+        // groups of batch_min..8 maps share one batched (MFMA) Legendre pass
+        const int nb = nmaps - i >= batch_min ? std::min(nmaps - i, psht::kMaxLegBatch) : 1;
+        char *ws0 = static_cast<char *>(workspace) + (size_t)i * plan->ws_per_map;
+        const size_t offQ = plan->ws_F + plan->ws_V + plan->ws_U;
+        const char *a0 = static_cast<const char *>(alm) + i * alm_bytes;
+        hipError_t e;
+        if (nb > 1)
+            e = timed(P, PSHT_T_LEG_SYNTH, st, [&] {
+                return psht::launch_leg_synth_batch(P, nb, a0, (int64_t)alm_bytes, ws0, ws0 + offQ,
+                                                    (int64_t)plan->ws_per_map, mscale, st);
+            });
+        else
+            e = timed(P, PSHT_T_LEG_SYNTH, st, [&] {
+                return psht::launch_leg_synth(P, a0, reinterpret_cast<double *>(ws0), ws0 + offQ, mscale, st);
+            });
+        for (int b = 0; b < nb && e == hipSuccess; ++b) {
+            char *ws = ws0 + (size_t)b * plan->ws_per_map;
+            double *F = reinterpret_cast<double *>(ws);
+            void *V = ws + plan->ws_F;
+            void *U = ws + plan->ws_F + plan->ws_V;
+            void *m = static_cast<char *>(map) + (size_t)(i + b) * map_bytes;
+            e = timed(P, PSHT_T_THETA_SYNTH, st, [&] { return psht::launch_theta_synth(P, F, V, st); });
+            if (e == hipSuccess) e = timed(P, PSHT_T_PHI_SYNTH, st, [&] { return psht::launch_phi_synth(P, V, U, st); });
+            if (e == hipSuccess) e = timed(P, PSHT_T_INTERP, st, [&] { return psht::launch_interp(P, U, m, st); });
+        }
         if (e != hipSuccess) return device_fail(e, "synthesis launch");
+        i += nb;
     }
     return PSHT_OK;
 }

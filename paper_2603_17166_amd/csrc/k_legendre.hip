@@ -445,6 +445,150 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     }
 }
 
+// ------------------------------------------------------- batched maps (MFMA)
+//
+// nb <= 8 coefficient sets on one plan.  For one order m and a chunk of 64
+// rings, the sums over l are the dense contraction
+//   F_b(+m)[j] = -sum_l lambda+_l(theta_j) Z+_b[l],  Z+_b = P (g_b + i c_b),
+//   F_b(-m)[j] = -(-1)^s sum_l lambda-_l(theta_j) Z-_b[l],
+// i.e. (64 rings x L) times (L x 16 real columns: 8 maps x {Re, Im}) for each
+// sign.  The recurrence runs once for all maps (one ring per lane); blocks of
+// 4 consecutive l go through LDS to the A operand of v_mfma_f64_16x16x4f64
+// (A[i][k] in lane i + 16 k: ring 16 q + i, l + k), the staged columns are the
+// B operand (B[k][j] in lane j + 16 k) and D accumulates in registers (D[i][j]
+// in lane j + 16 (i mod 4), register i / 4).
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+struct LegBatchArgs {
+    LegArgs a;           // work list of 64-ring chunks, tables, rings
+    const char *Q0;      // Q of map 0 (double4 per (l, m <= mmax)); map b at Q0 + b * stride
+    char *F0;            // F of map 0; map b at F0 + b * stride
+    int64_t stride;      // bytes between consecutive maps' Q and F
+    int nb;              // maps in this launch, 1..8
+};
+
+// (at most 168 VGPRs: three waves per SIMD measured faster than two)
+template <bool SPIN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_leg_synth_mm(LegBatchArgs bt) {
+    const LegArgs &a = bt.a;
+    __shared__ double4 sT[2][kStage];
+    __shared__ double sZ[2][kStage][2][16];  // [slot][l][sign][column]
+    __shared__ double sL[2][2][4][64];       // [buffer][sign][k][ring]
+    const int idx = leg_item_index(blockIdx.x, a.group);
+    if (idx >= a.nitems) return;
+    const LegItem it = a.items[idx];
+    if (it.je <= it.jb) return;
+    const int m = it.m, s = a.spin, lane = threadIdx.x;
+    const int l0 = m > s ? m : s, lmax = a.lmax;
+    if (l0 > lmax) return;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double4 *T4 = a.coef + base;
+
+    // Staging of a chunk of kStage steps from l = c: lanes 0..31 load the
+    // recurrence table, every lane 4 (l, map) entries of the columns
+    // (l = c + e / 8, map = e % 8), zero past lmax and past nb.  The loads of
+    // the next chunk are issued before the current chunk is computed and
+    // written to the other LDS slot after it.
+    auto load_z = [&](int c, int e) {
+        const int lo = e >> 3, b = e & 7, l = c + lo;
+        double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (b < bt.nb && l <= lmax)
+            v = reinterpret_cast<const double4 *>(bt.Q0 + (int64_t)b * bt.stride)[base + l];
+        return v;
+    };
+    auto store_z = [&](int slot, int e, double4 v) {
+        const int lo = e >> 3, b = e & 7;
+        sZ[slot][lo][0][2 * b] = v.x;
+        sZ[slot][lo][0][2 * b + 1] = v.y;
+        sZ[slot][lo][1][2 * b] = v.z;
+        sZ[slot][lo][1][2 * b + 1] = v.w;
+    };
+    if (lane < 32) sT[0][lane] = stage_entry(T4, nullptr, l0, lmax, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) store_z(0, lane + 64 * i, load_z(l0, lane + 64 * i));
+
+    LegState<1, SPIN> S;
+    leg_init<1, SPIN>(a, it, lane, S);
+    bool scaled = leg_any_scaled<1, SPIN>(S);
+    d4v Dp[4], Dm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Dp[q] = Dm[q] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int kk = lane >> 4, jj = lane & 15;
+    __syncthreads();
+
+    int slot = 0, buf = 0;
+    for (int c = l0; c <= lmax; c += kStage) {
+        const bool has_next = c + kStage <= lmax;
+        double4 nt, nz[4];
+        if (has_next) {
+            if (lane < 32) nt = stage_entry(T4, nullptr, c + kStage, lmax, lane);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) nz[i] = load_z(c + kStage, lane + 64 * i);
+        }
+        const int n = min(kStage, lmax + 1 - c);
+        for (int b4 = 0; b4 < n; b4 += 4) {
+            double cp = 1.0, cm = 1.0;
+            if (scaled) {
+                cp = S.kp[0] == 0 ? 1.0 : 0.0;
+                cm = (SPIN ? S.km[0] : S.kp[0]) == 0 ? 1.0 : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int t = b4 + k;
+                double vp = 0.0, vm = 0.0;
+                if (t < n) {
+                    vp = S.up[0] * cp;
+                    vm = (SPIN ? S.um[0] : S.up[0]) * cm;
+                    if (c + t < lmax) leg_advance<1, SPIN>(S, sT[slot][t]);
+                }
+                sL[buf][0][k][lane] = vp;
+                sL[buf][1][k][lane] = vm;
+            }
+            if (scaled) {
+                leg_renorm<1, SPIN>(S);
+                scaled = leg_any_scaled<1, SPIN>(S);
+            }
+            // One wave per workgroup: the barrier orders this block's LDS
+            // writes before its reads; the next block writes the other buffer.
+            __syncthreads();
+            // columns of l = c + b4 + kk (zero past lmax)
+            const double bp = sZ[slot][b4 + kk][0][jj], bm = sZ[slot][b4 + kk][1][jj];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Dp[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sL[buf][0][kk][16 * q + jj], bp, Dp[q], 0, 0, 0);
+                Dm[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sL[buf][1][kk][16 * q + jj], bm, Dm[q], 0, 0, 0);
+            }
+            buf ^= 1;
+        }
+        if (has_next) {
+            if (lane < 32) sT[slot ^ 1][lane] = nt;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) store_z(slot ^ 1, lane + 64 * i, nz[i]);
+        }
+        __syncthreads();
+        slot ^= 1;
+    }
+
+    // D[i][j] of block q: ring jb + 16 q + i, column j = 2 map + {Re, Im}
+    const double sgn_neg = (s & 1) ? 1.0 : -1.0;  // -(-1)^s
+    const int b = jj >> 1, comp = jj & 1;
+    if (b >= bt.nb) return;
+    double *F = reinterpret_cast<double *>(bt.F0 + (int64_t)b * bt.stride);
+    const int64_t op = 2 * ((int64_t)(a.mmax + m) * a.nring) + comp;
+    const int64_t om = 2 * ((int64_t)(a.mmax - m) * a.nring) + comp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = it.jb + 16 * q + kk + 4 * r;
+            if (j >= it.je || a.ring_mmax[j] < m) continue;
+            F[op + 2 * j] = -Dp[q][r];
+            if (m != 0) F[om + 2 * j] = sgn_neg * Dm[q][r];
+        }
+    }
+}
+
 template <int R>
 static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out, double *F) {
     const Geometry &g = p.g;
@@ -521,6 +665,33 @@ hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, vo
         case 8: leg_synth_r<8>(p, scratch, F, st); break;
         default: leg_synth_r<4>(p, scratch, F, st); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_synth_batch(const psht_plan_s &p, int nb, const void *alm0, int64_t alm_stride, char *F0,
+                                  char *Q0, int64_t ws_stride, double mscale, hipStream_t st) {
+    if (nb < 1 || nb > kMaxLegBatch) return hipErrorInvalidValue;
+    if (p.n_leg_items64 == 0) return hipSuccess;
+    const Geometry &g = p.g;
+    const int64_t n = leg_entries(g);
+    const int64_t nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
+    for (int b = 0; b < nb; ++b) {
+        const double2 *gg = reinterpret_cast<const double2 *>(static_cast<const char *>(alm0) + b * alm_stride);
+        hipLaunchKernelGGL(k_leg_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gg, gg + nalm,
+                           reinterpret_cast<const double4 *>(p.leg->d_coef),
+                           reinterpret_cast<double4 *>(Q0 + b * ws_stride), n, g.lmax, mscale);
+    }
+    LegBatchArgs bt;
+    bt.a = leg_args<1>(p, nullptr, nullptr, nullptr);
+    bt.a.items = p.d_leg_items64;
+    bt.a.nitems = p.n_leg_items64;
+    bt.a.group = (g.nring + 63) / 64;
+    bt.Q0 = Q0;
+    bt.F0 = F0;
+    bt.stride = ws_stride;
+    bt.nb = nb;
+    if (g.spin) hipLaunchKernelGGL((k_leg_synth_mm<true>), dim3(p.n_leg_items64), dim3(64), 0, st, bt);
+    else hipLaunchKernelGGL((k_leg_synth_mm<false>), dim3(p.n_leg_items64), dim3(64), 0, st, bt);
     return hipGetLastError();
 }
 

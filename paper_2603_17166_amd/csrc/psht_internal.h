@@ -108,6 +108,8 @@ struct psht_plan_s {
     psht::LegItem *d_leg_items = nullptr;
     int n_leg_items = 0;
     int leg_rings_per_item = 0;
+    psht::LegItem *d_leg_items64 = nullptr;  // 64-ring chunks (batched-maps kernel)
+    int n_leg_items64 = 0;
     std::shared_ptr<psht::LegTable> leg;
     // NUFFT tables
     double *d_psihat_t = nullptr, *d_psihat_p = nullptr;
@@ -140,6 +142,12 @@ hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, vo
                             hipStream_t st);
 size_t leg_synth_scratch_bytes(const Geometry &g);
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st);
+// Legendre synthesis of nb <= kMaxLegBatch maps in one pass (MFMA): map b reads
+// its coefficients at alm0 + b alm_stride and uses the F and Q buffers at
+// F0 + b ws_stride and Q0 + b ws_stride (its own workspace).
+constexpr int kMaxLegBatch = 8;
+hipError_t launch_leg_synth_batch(const psht_plan_s &p, int nb, const void *alm0, int64_t alm_stride, char *F0,
+                                  char *Q0, int64_t ws_stride, double mscale, hipStream_t st);
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st);
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st);
 hipError_t launch_phi_synth(const psht_plan_s &p, const void *V, void *U, hipStream_t st);
