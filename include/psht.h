@@ -95,6 +95,7 @@ typedef struct {
     int64_t npoints;
     size_t resident_bytes;          /* device memory the plan holds */
     size_t workspace_bytes_per_map; /* workspace psht_synth/psht_adjoint need per map */
+    double kernel_poly_err;  /* largest error of the polynomial ES kernel taps (inner taps) */
 } psht_plan_info;
 
 /* Build a plan for npoints points (device arrays theta, phi; read during the

@@ -45,6 +45,7 @@ class PlanInfo(ctypes.Structure):
         ("nufft_beta", ctypes.c_double), ("nufft_sigma", ctypes.c_double), ("predicted_speedup", ctypes.c_double),
         ("legendre_triples", ctypes.c_double),
         ("npoints", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t), ("workspace_bytes_per_map", ctypes.c_size_t),
+        ("kernel_poly_err", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

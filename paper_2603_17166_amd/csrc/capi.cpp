@@ -125,6 +125,7 @@ void fill_info(const psht_plan_s &p, psht_plan_info *info) {
     info->npoints = p.npts;
     info->resident_bytes = p.resident + (p.leg ? p.leg->bytes : 0);
     info->workspace_bytes_per_map = p.ws_per_map;
+    info->kernel_poly_err = g.es_poly_err;
 }
 
 struct ScopedDevFree {
@@ -238,7 +239,8 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     }
 
     // NUFFT tables
-    if (!upload(p, p.d_psihat_t, g.psihat_theta, st) || !upload(p, p.d_psihat_p, g.psihat_phi, st))
+    if (!upload(p, p.d_psihat_t, g.psihat_theta, st) || !upload(p, p.d_psihat_p, g.psihat_phi, st) ||
+        (!g.es_poly.empty() && !upload(p, p.d_es_poly, g.es_poly, st)))
         return fail(PSHT_ERR_NOMEM, "uploading kernel tables");
     if (!make_fft_table(p, p.fft_n2, g.N2, st) || !make_fft_table(p, p.fft_nt, g.Ntheta, st) ||
         !make_fft_table(p, p.fft_np, g.Nphi, st))

@@ -30,6 +30,7 @@ struct NufftArgs {
     const double *px, *py;
     const int32_t *perm;
     const int32_t *tile_start;
+    const double *poly;  // kernel polynomial table of the inner taps
 };
 
 __device__ __host__ inline int stencil_origin(double X, int W) { return (int)ceil(X - 0.5 * W); }
@@ -39,10 +40,43 @@ __device__ inline double es_kernel(double z, double beta) {
     return exp(beta * (sqrt(t) - 1.0));
 }
 
+// Kernel weights of the W taps of a point with grid coordinate X and stencil
+// origin a0: tap i has psi((X - a0 - i) 2 / W).  With v = 2 (X - a0) - (W - 1)
+// in [-1, 1], the inner taps 1..(W-1)/2 are polynomials of degree
+// max(W + 1, 12) in v
+// from the plan's table C (power-major) and tap W - 1 - i is the same
+// polynomial at -v: even and odd parts by Horner in v^2 give both.  The two
+// edge taps use the formula.
+// The table is wave-uniform: it is read through the scalar data cache into
+// SGPRs (constant address space), so the FMAs take it as scalar operands and
+// the LDS stays free for the tile subgrid.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) double *UniformPtr;
+__device__ inline UniformPtr uniform_ptr(const double *p) { return (UniformPtr)p; }
+#else
+typedef const double *UniformPtr;
+__host__ __device__ inline UniformPtr uniform_ptr(const double *p) { return p; }
+#endif
+
 template <int W>
-__device__ inline void es_weights(double X, int a0, double beta, double *k) {
+__device__ inline void es_weights(double X, int a0, double beta, UniformPtr C, double *k) {
+    constexpr int P = W + 1 > 12 ? W + 1 : 12, NC = (W - 1) / 2;
+    constexpr int PE = (P % 2 == 0) ? P : P - 1, PO = (P % 2 == 1) ? P : P - 1;
+    const double v = 2.0 * (X - (double)a0) - (double)(W - 1), v2 = v * v;
+    k[0] = es_kernel((v + (double)(W - 1)) * (1.0 / W), beta);
+    k[W - 1] = es_kernel((v - (double)(W - 1)) * (1.0 / W), beta);
 #pragma unroll
-    for (int i = 0; i < W; ++i) k[i] = es_kernel((X - (double)(a0 + i)) * (2.0 / W), beta);
+    for (int c = 0; c < NC; ++c) {
+        double e = C[PE * NC + c];
+#pragma unroll
+        for (int q = PE - 2; q >= 0; q -= 2) e = fma(e, v2, C[q * NC + c]);
+        double o = C[PO * NC + c];
+#pragma unroll
+        for (int q = PO - 2; q >= 1; q -= 2) o = fma(o, v2, C[q * NC + c]);
+        o *= v;
+        k[c + 1] = e + o;
+        if (W - 2 - c != c + 1) k[W - 2 - c] = e - o;
+    }
 }
 
 template <typename T> struct CplxT;
@@ -56,6 +90,7 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
     typedef typename CplxT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *S = reinterpret_cast<C *>(smem);
+    const UniformPtr sC = uniform_ptr(a.poly);
     const int t = blockIdx.x;
     const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
     if (p0 == p1) return;
@@ -82,8 +117,8 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         // guard only keeps LDS accesses in bounds.
         if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
         double kx[W], ky[W];
-        es_weights<W>(X, a0, a.beta, kx);
-        es_weights<W>(Y, b0, a.beta, ky);
+        es_weights<W>(X, a0, a.beta, sC, kx);
+        es_weights<W>(Y, b0, a.beta, sC, ky);
         double accr = 0.0, acci = 0.0;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -120,6 +155,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
     // precisions: the FP64 LDS atomic add is a native fast path on gfx950,
     // while FP32 LDS atomic adds measured an order of magnitude slower.
     double *Sre = reinterpret_cast<double *>(smem), *Sim = Sre + SX * SYP;
+    const UniformPtr sC = uniform_ptr(a.poly);
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
     for (int e = threadIdx.x; e < 2 * SX * SYP; e += kTileThreads) Sre[e] = 0.0;
     __syncthreads();
@@ -131,8 +167,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         const int li = a0 - a.row_lo - r0, lj = b0m - c0;
         if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
         double kx[W], ky[W];
-        es_weights<W>(X, a0, a.beta, kx);
-        es_weights<W>(Y, b0, a.beta, ky);
+        es_weights<W>(X, a0, a.beta, sC, kx);
+        es_weights<W>(Y, b0, a.beta, sC, ky);
         const C f = map[a.perm[p]];
         const double fr = f.x, fi = f.y;
 #pragma unroll
@@ -175,6 +211,7 @@ static NufftArgs nufft_args(const psht_plan_s &p) {
     a.py = p.d_py;
     a.perm = p.d_perm;
     a.tile_start = p.d_tile_start;
+    a.poly = p.d_es_poly;
     return a;
 }
 

@@ -121,6 +121,70 @@ static double es_psihat(ld k, int W, ld beta, ld h, const GL &gl) {
     return (double)(s * (kPiL / 2) * W / 2);
 }
 
+// ES kernel psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1, in long double.
+static ld es_psi(ld z, ld beta) {
+    ld t = 1 - z * z;
+    if (t < 0) t = 0;
+    return expl(beta * (sqrtl(t) - 1));
+}
+
+// Polynomial form of the inner kernel taps.  For a stencil origin a0 and
+// v = 2 (X - a0) - (W - 1) in [-1, 1], tap i has weight g_i(v) = psi(z) with
+// z = (v + W - 1 - 2 i) / W; tap W - 1 - i is g_i(-v).  Each inner tap
+// i = 1..(W-1)/2 is interpolated at the P + 1 Chebyshev points of [-1, 1]
+// (degree P = max(W + 1, 12)), converted to powers of v, and checked against psi on a
+// fine grid with the device's evaluation order (even and odd parts by Horner
+// in v^2).  The two edge taps reach |z| = 1, where sqrt(1 - z^2) has a
+// vertical tangent that polynomials resolve slowly; they keep the formula.
+static void es_poly_table(Geometry &g) {
+    const int W = g.W, P = W + 1 > 12 ? W + 1 : 12, NC = (W - 1) / 2, n = P + 1;
+    const ld beta = g.beta;
+    g.es_poly.assign((size_t)n * NC, 0.0);
+    double worst = 0;
+    for (int c = 0; c < NC; ++c) {
+        const int i = c + 1;
+        auto f = [&](ld v) { return es_psi((v + W - 1 - 2 * i) / (ld)W, beta); };
+        std::vector<ld> fx(n), a(n, 0);
+        for (int k = 0; k < n; ++k) fx[k] = f(cosl(kPiL * (k + 0.5L) / n));
+        for (int j = 0; j < n; ++j) {
+            ld sum = 0;
+            for (int k = 0; k < n; ++k) sum += fx[k] * cosl(kPiL * j * (k + 0.5L) / n);
+            a[j] = sum * 2 / n;
+        }
+        a[0] /= 2;
+        // sum_j a_j T_j(v) in powers of v (T_{j+1} = 2 v T_j - T_{j-1})
+        std::vector<ld> mono(n, 0), tm1(n, 0), t0(n, 0), t1(n, 0);
+        t0[0] = 1;
+        mono[0] += a[0];
+        if (n > 1) {
+            t1[1] = 1;
+            mono[1] += a[1];
+        }
+        for (int j = 2; j < n; ++j) {
+            std::vector<ld> t2(n, 0);
+            for (int q = 0; q + 1 < n; ++q) t2[q + 1] += 2 * t1[q];
+            for (int q = 0; q < n; ++q) t2[q] -= t0[q];
+            for (int q = 0; q < n; ++q) mono[q] += a[j] * t2[q];
+            t0 = t1;
+            t1 = t2;
+        }
+        for (int q = 0; q < n; ++q) g.es_poly[(size_t)q * NC + c] = (double)mono[q];
+        // check in double, in the device's order
+        const int PE = (P % 2 == 0) ? P : P - 1, PO = (P % 2 == 1) ? P : P - 1;
+        for (int t = 0; t <= 400; ++t) {
+            const double v = -1.0 + t / 200.0, v2 = v * v;
+            double e = g.es_poly[(size_t)PE * NC + c];
+            for (int q = PE - 2; q >= 0; q -= 2) e = std::fma(e, v2, g.es_poly[(size_t)q * NC + c]);
+            double o = g.es_poly[(size_t)PO * NC + c];
+            for (int q = PO - 2; q >= 1; q -= 2) o = std::fma(o, v2, g.es_poly[(size_t)q * NC + c]);
+            o *= v;
+            worst = std::max(worst, (double)fabsl((ld)(e + o) - f(v)));
+            worst = std::max(worst, (double)fabsl((ld)(e - o) - f(-v)));
+        }
+    }
+    g.es_poly_err = worst;
+}
+
 // ---------------------------------------------------- polar cut-off search
 
 // Is max over l <= lmax of max(|lambda+_lm(theta)|, |lambda-_lm(theta)|) >= tau?
@@ -295,6 +359,11 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
     g.W = es_width(eps);
     g.beta = es_beta(g.W);
     g.sigma = 2.0;
+    es_poly_table(g);
+    if (g.es_poly_err > std::max(1e-3 * eps, 1e-14)) {
+        err = {PSHT_ERR_UNSUPPORTED, "kernel polynomial table not accurate enough"};
+        return false;
+    }
     g.Ntheta = 2 * g.N2;
     while (g.Ntheta < 2 * g.W + 4) g.Ntheta += 2 * g.N2;
     int np = std::max(2 * (2 * g.mmax + 1), 2 * g.W + 4);

@@ -45,6 +45,12 @@ struct Geometry {
     double sx = 0, sy = 0;           // grid coordinate = theta*sx (rows), phi*sy (cols)
     std::vector<double> psihat_theta; // n = 0..Lmax
     std::vector<double> psihat_phi;   // m = 0..mmax
+    // ES kernel on the inner taps 1..(W-1)/2 as polynomials of degree
+    // P = max(W + 1, 12) in v = 2 (X - a0) - (W - 1), [P + 1][(W - 1) / 2]
+    // (power-major); the mirror taps follow from v -> -v.  es_poly_err:
+    // largest error on a test grid.
+    std::vector<double> es_poly;
+    double es_poly_err = 0;
     double predicted_speedup = 0;
     double legendre_triples = 0;
 };
@@ -113,6 +119,7 @@ struct psht_plan_s {
     std::shared_ptr<psht::LegTable> leg;
     // NUFFT tables
     double *d_psihat_t = nullptr, *d_psihat_p = nullptr;
+    double *d_es_poly = nullptr;
     psht::FftTable fft_n2, fft_nt, fft_np, fft_np_half;
     bool phi_split = false;
     // points, sorted by tile

@@ -186,3 +186,12 @@ def test_invalid_arguments():
         with pytest.raises(_lib.PshtError) as e:
             plan_geometry(*args)
         assert e.value.code == _lib.PSHT_ERR_ARG
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-5, 1e-6, 1e-8, 1e-10, 1e-12, 1e-14])
+def test_kernel_polynomial_table_accuracy(eps):
+    """The inner ES kernel taps are evaluated from polynomials; the plan
+    checks them against the kernel formula on a fine grid (both signs of the
+    offset) and reports the largest error, which must stay far below eps."""
+    info = plan_geometry(256, 2, 0.3, eps, "auto")[0]
+    assert 0.0 < info["kernel_poly_err"] <= max(1e-3 * eps, 1e-14)
