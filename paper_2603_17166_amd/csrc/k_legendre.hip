@@ -200,7 +200,7 @@ template <int R, bool SPIN> __device__ inline void leg_masks(const LegState<R, S
 
 template <int R, bool SPIN>
 __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
-    __shared__ double4 sbuf[2][2][kStage];
+    __shared__ double4 sbuf[2][2][kStage + 1];  // one spare entry: the pipelined loop reads one step ahead
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
@@ -230,10 +230,28 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
         const double4 *sT = sbuf[slot][0], *sQ = sbuf[slot][1];
         const int n = min(kStage, lmax + 1 - c);
         if (!scaled && has_next) {
-            // full chunk, every step advances, no lane scaled: no per-step guards
+            // Full chunk, every step advances, no lane scaled: no per-step guards.
+            // The coefficients of step t + 1 are read while step t computes.
+            double4 q = sQ[0], tc = sT[0];
 #pragma unroll 4
             for (int t = 0; t < kStage; ++t) {
-                const double4 q = sQ[t];
+                double4 qn = sQ[t + 1], tn;
+                tn.x = sT[t + 1].x;
+                tn.y = sT[t + 1].y;
+                tn.z = sT[t + 1].z;
+                tn.w = 0.0;
+                // keep these loads ahead of the arithmetic of step t
+                __builtin_amdgcn_sched_barrier(0);
+                // Independent work first, dependent updates last, so that no
+                // FMA waits for the one just before it: the step coefficients
+                // (A +/- B) - A y of every ring, the accumulation of lambda_l,
+                // then the recurrence updates that use both.
+                double cpl[R], cmi[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cpl[r] = fma(tc.x, S.y[r], tc.y);
+                    if (SPIN) cmi[r] = fma(tc.x, S.y[r], tc.z);
+                }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const double vm = SPIN ? S.um[r] : S.up[r];
@@ -242,7 +260,20 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
                     fmr[r] = fma(q.z, vm, fmr[r]);
                     fmi[r] = fma(q.w, vm, fmi[r]);
                 }
-                leg_advance<R, SPIN>(S, sT[t]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double np = fma(cpl[r], S.up[r], -S.upp[r]);
+                    S.upp[r] = S.up[r];
+                    S.up[r] = np;
+                    if (SPIN) {
+                        const double nm = fma(cmi[r], S.um[r], -S.ump[r]);
+                        S.ump[r] = S.um[r];
+                        S.um[r] = nm;
+                    }
+                }
+                q = qn;
+                tc = tn;
             }
         } else for (int b = 0; b < n; b += 8) {
             const int e = min(b + 8, n);
@@ -276,7 +307,6 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
 
 // ---------------------------------------------------------------- adjoint
 
-constexpr int kAdjChunk = 8;  // l per transposed reduction
 
 // Swap the upper 32 lanes of x with the lower 32 lanes of y (64-bit values).
 __device__ inline void swap32(double &x, double &y) {
@@ -296,10 +326,12 @@ __device__ inline void swap16(double &x, double &y) {
     y = __hiloint2double(hi[1], lo[1]);
 }
 
-template <int R, bool SPIN>
+// CH: values of l per transposed reduction (4 or 8).
+template <int R, bool SPIN, int CH>
 __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
+    constexpr int kAdjChunk = CH, NV = 4 * CH;  // NV partial sums per lane per block
     __shared__ double4 sbuf[2][kStage];
-    __shared__ double red[4][kAdjChunk][17];
+    __shared__ double red[4][NV / 4][17];
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
@@ -350,6 +382,15 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
             if (plain) {
 #pragma unroll
                 for (int u = 0; u < kAdjChunk; ++u) {
+                    // independent work first (step coefficients, partial sums),
+                    // the dependent recurrence updates last
+                    const double4 tc = sT[b + u];
+                    double cpl[R], cmi[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        cpl[r] = fma(tc.x, S.y[r], tc.y);
+                        if (SPIN) cmi[r] = fma(tc.x, S.y[r], tc.z);
+                    }
                     double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -359,7 +400,17 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                         pb_r = fma(vm, fmr[r], pb_r);
                         pb_i = fma(vm, fmi[r], pb_i);
                     }
-                    leg_advance<R, SPIN>(S, sT[b + u]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double np = fma(cpl[r], S.up[r], -S.upp[r]);
+                        S.upp[r] = S.up[r];
+                        S.up[r] = np;
+                        if (SPIN) {
+                            const double nm = fma(cmi[r], S.um[r], -S.ump[r]);
+                            S.ump[r] = S.um[r];
+                            S.um[r] = nm;
+                        }
+                    }
                     v[4 * u + 0] = pa_r;
                     v[4 * u + 1] = pa_i;
                     v[4 * u + 2] = pb_r;
@@ -395,31 +446,34 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                 scaled = leg_any_scaled<R, SPIN>(S);
             }
             // Transposed reduction over the 64 lanes: two permlane stages leave each
-            // lane with 8 values summed over lanes {i, i^16, i^32, i^48}; value k of
-            // lane i then stands for index k + 8*bit4(i) + 16*bit5(i) of v.
+            // lane with NV/4 values summed over lanes {i, i^16, i^32, i^48}; value k
+            // of lane i then stands for index k + (NV/4) bit4(i) + (NV/2) bit5(i) of v.
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                swap32(v[k], v[k + 16]);
-                v[k] += v[k + 16];
+            for (int k = 0; k < NV / 2; ++k) {
+                swap32(v[k], v[k + NV / 2]);
+                v[k] += v[k + NV / 2];
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                swap16(v[k], v[k + 8]);
-                v[k] += v[k + 8];
+            for (int k = 0; k < NV / 4; ++k) {
+                swap16(v[k], v[k + NV / 4]);
+                v[k] += v[k + NV / 4];
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) red[row][k][col] = v[k];
+            for (int k = 0; k < NV / 4; ++k) red[row][k][col] = v[k];
             __syncthreads();
-            // output o = (row q, value k) summed over the 16 lanes of row q, two lanes per output
-            const int o = lane & 31, hh = lane >> 5;
-            const int q = o >> 3, k = o & 7;
+            // output o = (row q, value k), o = q NV/4 + k, is the sum over the 16
+            // lanes of row q; 64/NV lanes share an output and each sums NV/4 of them
+            constexpr int PARTS = 64 / NV, PER = 16 / PARTS;
+            const int o = lane & (NV - 1), hh = lane / NV;
+            const int q = o / (NV / 4), k = o % (NV / 4);
             double sum = 0.0;
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) sum += red[q][k][8 * hh + jj];
-            sum += __shfl_xor(sum, 32);
-            // global index k + 8 (q & 1) + 16 (q >> 1) = 4 u + c: quads of lanes hold the 4 components of one l
-            const int gidx = k + 8 * (q & 1) + 16 * (q >> 1);
-            const int u = gidx >> 2, cc = gidx & 3;
+            for (int jj = 0; jj < PER; ++jj) sum += red[q][k][PER * hh + jj];
+#pragma unroll
+            for (int sh = NV; sh < 64; sh <<= 1) sum += __shfl_xor(sum, sh);
+            // global index k + (NV/4)(q & 1) + (NV/2)(q >> 1) = o = 4 u + c: quads of
+            // lanes hold the 4 components of one l
+            const int u = o >> 2, cc = o & 3;
             const int qb = lane & ~3;
             const double s0 = __shfl(sum, qb | 0), s1 = __shfl(sum, qb | 1), s2 = __shfl(sum, qb | 2),
                          s3 = __shfl(sum, qb | 3);
@@ -641,13 +695,27 @@ static void leg_synth_r(const psht_plan_s &p, const void *Q, double *F, hipStrea
     else hipLaunchKernelGGL((k_leg_synth<R, false>), grid, block, 0, st, a);
 }
 
+// l per transposed reduction of the adjoint: 8 unless PSHT_ADJ_CH=4 for tuning runs.
+static int leg_adj_chunk() {
+    static int c = [] {
+        const char *e = getenv("PSHT_ADJ_CH");
+        return (e && atoi(e) == 4) ? 4 : 8;
+    }();
+    return c;
+}
+
 template <int R>
 static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
     LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
     a.mscale = mscale;
     dim3 grid(p.n_leg_items), block(64);
-    if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_leg_adjoint<R, false>), grid, block, 0, st, a);
+    if (leg_adj_chunk() == 4) {
+        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 4>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 4>), grid, block, 0, st, a);
+    } else {
+        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8>), grid, block, 0, st, a);
+    }
 }
 
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, double mscale,
