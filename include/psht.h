@@ -100,7 +100,7 @@ typedef struct {
 
 /* Build a plan for npoints points (device arrays theta, phi; read during the
  * call only, not kept).  Validates lmax >= 0, 0 <= spin <= lmax,
- * 1e-14 <= epsilon <= 1e-2, npoints >= 0 and < 2^31, every theta in
+ * 1e-14 <= epsilon <= 1e-2, npoints >= 0 and < 2^30, every theta in
  * [0, pi] and every phi finite (checked on the device; one device-to-host
  * synchronisation on `hip_stream`).  Sorts the points into NUFFT tiles and
  * uploads rings, window weights, per-ring m cut-offs and kernel tables; the

@@ -143,7 +143,8 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     if (lmax > 16384) return fail(PSHT_ERR_UNSUPPORTED, "lmax above 16384");
     if (!(epsilon >= 1e-14 && epsilon <= 1e-2)) return fail(PSHT_ERR_ARG, "epsilon must lie in [1e-14, 1e-2]");
     if (precision < PSHT_PREC_AUTO || precision > PSHT_PREC_FP64) return fail(PSHT_ERR_ARG, "unknown precision");
-    if (npoints < 0 || npoints >= (int64_t(1) << 31)) return fail(PSHT_ERR_ARG, "npoints must lie in [0, 2^31)");
+    // the slot layout of the sorted points (at most two entries per point) is indexed in int32
+    if (npoints < 0 || npoints >= (int64_t(1) << 30)) return fail(PSHT_ERR_ARG, "npoints must lie in [0, 2^30)");
     if (npoints > 0 && (!theta || !phi)) return fail(PSHT_ERR_ARG, "theta/phi are NULL");
 
     // theta range and validity (one device-to-host synchronisation)
@@ -259,21 +260,33 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     p.ntx = (g.rows_used + p.tile_x - 1) / p.tile_x;
     p.nty = (g.Nphi + p.tile_y - 1) / p.tile_y;
     p.ntiles = p.ntx * p.nty;
-    if (!dalloc(p, p.d_px, (size_t)npoints) || !dalloc(p, p.d_py, (size_t)npoints) ||
-        !dalloc(p, p.d_perm, (size_t)npoints) || !dalloc(p, p.d_tile_start, (size_t)p.ntiles + 1))
-        return fail(PSHT_ERR_NOMEM, "allocating sorted points");
+    if (!dalloc(p, p.d_tile_start, (size_t)p.ntiles + 1)) return fail(PSHT_ERR_NOMEM, "allocating sorted points");
     {
-        ScopedDevFree keys, cursor, tpx, tpy, tperm;
+        ScopedDevFree keys, cursor, pstart, tpx, tpy, tperm;
         const size_t nn = (size_t)std::max<int64_t>(npoints, 1);
         hipError_t e = hipMalloc(&keys.p, sizeof(int32_t) * nn);
         if (e == hipSuccess) e = hipMalloc(&cursor.p, sizeof(int32_t) * (size_t)p.ntiles);
+        if (e == hipSuccess) e = hipMalloc(&pstart.p, sizeof(int32_t) * ((size_t)p.ntiles + 1));
         if (e == hipSuccess) e = hipMalloc(&tpx.p, sizeof(double) * nn);
         if (e == hipSuccess) e = hipMalloc(&tpy.p, sizeof(double) * nn);
         if (e == hipSuccess) e = hipMalloc(&tperm.p, sizeof(int32_t) * nn);
         if (e != hipSuccess) return device_fail(e, "sort scratch");
-        e = psht::launch_point_sort(p, theta, phi, static_cast<int32_t *>(keys.p), static_cast<int32_t *>(cursor.p),
-                                    static_cast<double *>(tpx.p), static_cast<double *>(tpy.p),
-                                    static_cast<int32_t *>(tperm.p), st);
+        e = psht::launch_point_sort_count(p, theta, phi, static_cast<int32_t *>(keys.p),
+                                          static_cast<int32_t *>(cursor.p), static_cast<int32_t *>(pstart.p),
+                                          static_cast<double *>(tpx.p), static_cast<double *>(tpy.p),
+                                          static_cast<int32_t *>(tperm.p), st);
+        int32_t total = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&total, p.d_tile_start + p.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(e, "point sort");
+        p.n_entries = total;
+        const size_t ne = (size_t)std::max<int64_t>(p.n_entries, 1);
+        if (!dalloc(p, p.d_px, ne) || !dalloc(p, p.d_py, ne) || !dalloc(p, p.d_perm, ne))
+            return fail(PSHT_ERR_NOMEM, "allocating sorted points");
+        e = psht::launch_point_sort_order(p, static_cast<int32_t *>(keys.p), static_cast<const int32_t *>(pstart.p),
+                                          static_cast<const double *>(tpx.p), static_cast<const double *>(tpy.p),
+                                          static_cast<const int32_t *>(tperm.p), st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return device_fail(e, "point sort");
     }

@@ -12,7 +12,9 @@
 //
 // Tiles: the points are bucket-sorted by the tile of (a0, b0); a tile covers
 // tile_x x tile_y stencil origins, so its points touch a (tile_x + W - 1) x
-// (tile_y + W - 1) subgrid.  One workgroup per tile stages that subgrid in
+// (tile_y + W - 1) subgrid.  Inside a tile the points come in slots of two
+// sharing their stencil origin (see k_tile_order); spreading gives a thread
+// one slot, interpolation one entry.  One workgroup per tile stages that subgrid in
 // LDS: interpolation reads it once from HBM; spreading accumulates into it
 // (in double) with LDS atomics and flushes it with one global atomic per
 // non-zero cell and component.
@@ -107,7 +109,11 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         S[e] = v;
     }
     __syncthreads();
+    // one entry per thread; the two entries of a slot (same cell) sit in
+    // neighbouring lanes, whose identical LDS reads are broadcasts
     for (int p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
+        const int pm = a.perm[p];
+        if (pm < 0) continue;  // dummy entry of an odd cell
         const double X = a.px[p], Y = a.py[p];
         const int a0 = stencil_origin(X, W), b0 = stencil_origin(Y, W);
         int b0m = b0 % a.Nphi;
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         C out;
         out.x = (T)accr;
         out.y = (T)acci;
-        map[a.perm[p]] = out;
+        map[pm] = out;
     }
 }
 
@@ -159,26 +165,37 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
     for (int e = threadIdx.x; e < 2 * SX * SYP; e += kTileThreads) Sre[e] = 0.0;
     __syncthreads();
-    for (int p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
-        const double X = a.px[p], Y = a.py[p];
+    // one slot per thread: both points share the stencil cells, so their
+    // contributions are summed in registers and each cell gets one LDS update
+    for (int q = (p0 >> 1) + threadIdx.x; q < (p1 >> 1); q += kTileThreads) {
+        const int p = 2 * q;
+        const double X = a.px[p], Y = a.py[p], X2 = a.px[p + 1], Y2 = a.py[p + 1];
         const int a0 = stencil_origin(X, W), b0 = stencil_origin(Y, W);
         int b0m = b0 % a.Nphi;
         if (b0m < 0) b0m += a.Nphi;
         const int li = a0 - a.row_lo - r0, lj = b0m - c0;
         if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
-        double kx[W], ky[W];
+        double kx[W], ky[W], kx2[W], ky2[W];
         es_weights<W>(X, a0, a.beta, sC, kx);
         es_weights<W>(Y, b0, a.beta, sC, ky);
+        // the partner has the same cell, but its own unwrapped origin: across
+        // phi = 0 its b0 differs from this point's by Nphi
+        es_weights<W>(X2, stencil_origin(X2, W), a.beta, sC, kx2);
+        es_weights<W>(Y2, stencil_origin(Y2, W), a.beta, sC, ky2);
         const C f = map[a.perm[p]];
-        const double fr = f.x, fi = f.y;
+        const int pm2 = a.perm[p + 1];
+        C f2;
+        f2.x = f2.y = (T)0;
+        if (pm2 >= 0) f2 = map[pm2];
+        const double fr = f.x, fi = f.y, fr2 = f2.x, fi2 = f2.y;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             double *Rre = Sre + (li + i) * SYP + lj, *Rim = Sim + (li + i) * SYP + lj;
-            const double wr = kx[i] * fr, wi = kx[i] * fi;
+            const double wr = kx[i] * fr, wi = kx[i] * fi, wr2 = kx2[i] * fr2, wi2 = kx2[i] * fi2;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(Rre + j, wr * ky[j]);
-                atomicAdd(Rim + j, wi * ky[j]);
+                atomicAdd(Rre + j, fma(wr, ky[j], wr2 * ky2[j]));
+                atomicAdd(Rim + j, fma(wi, ky[j], wi2 * ky2[j]));
             }
         }
     }
@@ -411,14 +428,17 @@ __global__ void k_point_scatter(SortArgs a, const double *theta, const double *p
     perm[pos] = (int32_t)i;
 }
 
-// Order inside a tile.  Points are ranked within their stencil-origin cell
-// (0 for the first point of a cell, 1 for the second, ...) and laid out rank
-// by rank, each rank level in row-major cell order.  Consecutive lanes of a
-// wave then take points of distinct, mostly adjacent cells, so the W x W
-// stencils they update or read in LDS in one instruction hit distinct
-// addresses in distinct banks.  Ranks from kRankLevels - 1 up share the last
-// level (in arbitrary order), which bounds the work for cells holding very
-// many points.
+// Order inside a tile.  The points of a tile are laid out in slots of two
+// entries: the two points of a slot share their stencil-origin cell (the
+// second entry is a dummy with perm = -1 when a cell has an odd count), so a
+// thread spreading a slot adds both points' contributions in registers before
+// each LDS update, and a thread interpolating a slot reads every subgrid value
+// once for both.  Points are ranked within their cell (0, 1, 2, ...), slot
+// rank = rank / 2, and slots are laid out rank by rank, each rank level in
+// row-major cell order: consecutive lanes of a wave then take slots of
+// distinct, mostly adjacent cells, so the W x W stencils they update in one
+// instruction hit distinct LDS addresses.  Slot ranks from kRankLevels - 1 up
+// share the last level, which bounds the work for cells with very many points.
 constexpr int kRankLevels = 16;
 constexpr int kOrderThreads = 256;
 
@@ -457,47 +477,84 @@ __device__ inline int block_exclusive_scan(int32_t *v, int n, int32_t *part) {
     return total;
 }
 
-// One workgroup per tile: reorders the tile's points from (tpx, tpy, tperm)
-// into (px, py, perm).  rank[] is per-point scratch.
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const int32_t *tile_start,
-                                                              const double *tpx, const double *tpy,
-                                                              const int32_t *tperm, int32_t *rank, double *px,
-                                                              double *py, int32_t *perm) {
+// Entries (2 per slot) of every tile: sum over cells of 2 ceil(count / 2).
+__global__ __launch_bounds__(kOrderThreads) void k_tile_entries(SortArgs a, const int32_t *pstart,
+                                                                const double *tpx, const double *tpy,
+                                                                int32_t *entries) {
+    extern __shared__ int32_t osm[];
+    const int C = a.tile_x * a.tile_y;
+    int32_t *cnt = osm;
+    __shared__ int32_t s_tot;
+    const int t = blockIdx.x;
+    const int p0 = pstart[t], p1 = pstart[t + 1];
+    if (p0 == p1) {
+        if (threadIdx.x == 0) entries[t] = 0;
+        return;
+    }
+    const int r0 = (t / a.nty) * a.tile_x, c0 = (t % a.nty) * a.tile_y;
+    for (int c = threadIdx.x; c < C; c += kOrderThreads) cnt[c] = 0;
+    if (threadIdx.x == 0) s_tot = 0;
+    __syncthreads();
+    for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads)
+        atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
+    __syncthreads();
+    int loc = 0;
+    for (int c = threadIdx.x; c < C; c += kOrderThreads) loc += 2 * ((cnt[c] + 1) / 2);
+    atomicAdd(&s_tot, loc);
+    __syncthreads();
+    if (threadIdx.x == 0) entries[t] = s_tot;
+}
+
+// One workgroup per tile: writes the tile's slots from (tpx, tpy, tperm)
+// (points [pstart[t], pstart[t+1]) in arbitrary order) to entries
+// [estart[t], estart[t+1]) of (px, py, perm).  rank[] is per-point scratch.
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const int32_t *pstart,
+                                                              const int32_t *estart, const double *tpx,
+                                                              const double *tpy, const int32_t *tperm,
+                                                              int32_t *rank, double *px, double *py, int32_t *perm) {
     extern __shared__ int32_t osm[];
     const int C = a.tile_x * a.tile_y;
     int32_t *cnt = osm, *pos = osm + C, *part = osm + 2 * C;
-    __shared__ int32_t s_kmax, s_cursor;
+    __shared__ int32_t s_kmax;
     const int t = blockIdx.x;
-    const int p0 = tile_start[t], p1 = tile_start[t + 1];
+    const int p0 = pstart[t], p1 = pstart[t + 1];
     if (p0 == p1) return;
+    const int e0 = estart[t];
     const int r0 = (t / a.nty) * a.tile_x, c0 = (t % a.nty) * a.tile_y;
     for (int c = threadIdx.x; c < C; c += kOrderThreads) cnt[c] = 0;
-    if (threadIdx.x == 0) {
-        s_kmax = 0;
-        s_cursor = 0;
-    }
+    if (threadIdx.x == 0) s_kmax = 0;
     __syncthreads();
     for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
         const int r = atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
         rank[p] = r;
-        atomicMax(&s_kmax, r + 1);
+        atomicMax(&s_kmax, r / 2 + 1);
     }
     __syncthreads();
     const int levels = min(s_kmax, kRankLevels);
-    int base = p0;
+    int base = 0;  // slots before this level
     for (int lev = 0; lev < levels; ++lev) {
         const bool last = lev == kRankLevels - 1;
-        for (int c = threadIdx.x; c < C; c += kOrderThreads) pos[c] = cnt[c] > lev ? (last ? cnt[c] - lev : 1) : 0;
+        // slots of this level per cell: 1, or every remaining slot on the last level
+        for (int c = threadIdx.x; c < C; c += kOrderThreads) {
+            const int sl = (cnt[c] + 1) / 2;  // slots of the cell
+            pos[c] = sl > lev ? (last ? sl - lev : 1) : 0;
+        }
         __syncthreads();
         const int n_lev = block_exclusive_scan(pos, C, part);
         for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
-            const int r = rank[p];
-            if (r < lev || (r > lev && !last)) continue;
+            const int r = rank[p], sr = r / 2;
+            if (sr < lev || (sr > lev && !last)) continue;
             const int cell = cell_in_tile(a, tpx[p], tpy[p], r0, c0);
-            const int dst = base + pos[cell] + (last ? r - lev : 0);
+            const int slot = base + pos[cell] + (last ? sr - lev : 0);
+            const int dst = e0 + 2 * slot + (r & 1);
             px[dst] = tpx[p];
             py[dst] = tpy[p];
             perm[dst] = tperm[p];
+            if (r == cnt[cell] - 1 && !(r & 1)) {  // odd cell: the slot's second entry is a dummy
+                px[dst + 1] = tpx[p];
+                py[dst + 1] = tpy[p];
+                perm[dst + 1] = -1;
+            }
         }
         base += n_lev;
         __syncthreads();
@@ -508,8 +565,7 @@ size_t tile_order_lds_bytes(int tile_x, int tile_y) {
     return sizeof(int32_t) * (2 * (size_t)tile_x * tile_y + kOrderThreads);
 }
 
-hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
-                             int32_t *d_cursor, double *tpx, double *tpy, int32_t *tperm, hipStream_t st) {
+static SortArgs sort_args(const psht_plan_s &p) {
     SortArgs a;
     a.sx = p.g.sx;
     a.sy = p.g.sy;
@@ -521,6 +577,13 @@ hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *
     a.tile_y = p.tile_y;
     a.ntx = p.ntx;
     a.nty = p.nty;
+    return a;
+}
+
+hipError_t launch_point_sort_count(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
+                                   int32_t *d_cursor, int32_t *d_pstart, double *tpx, double *tpy, int32_t *tperm,
+                                   hipStream_t st) {
+    const SortArgs a = sort_args(p);
     const int64_t n = p.npts;
     hipError_t e = launch_fill_zero(d_cursor, sizeof(int32_t) * (size_t)p.ntiles, st);
     if (e != hipSuccess) return e;
@@ -528,18 +591,29 @@ hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *
         unsigned nb = (unsigned)((n + 255) / 256);
         hipLaunchKernelGGL(k_point_keys, dim3(nb), dim3(256), 0, st, a, theta, phi, n, d_keys, d_cursor);
     }
-    // d_cursor now holds the counts; scan into tile_start and reuse d_cursor as the cursor
+    // d_cursor now holds the counts; scan into pstart and reuse d_cursor as the cursor
     // (the scan reads each count before it overwrites it within the same thread).
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cursor, p.ntiles, p.d_tile_start, d_cursor);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cursor, p.ntiles, d_pstart, d_cursor);
     if (n > 0) {
         unsigned nb = (unsigned)((n + 255) / 256);
         hipLaunchKernelGGL(k_point_scatter, dim3(nb), dim3(256), 0, st, a, theta, phi, n, d_keys, d_cursor, tpx, tpy,
                            tperm);
-        // keys are no longer needed: they hold the per-point ranks from here on
-        hipLaunchKernelGGL(k_tile_order, dim3((unsigned)p.ntiles), dim3(kOrderThreads),
-                           tile_order_lds_bytes(p.tile_x, p.tile_y), st, a, p.d_tile_start, tpx, tpy, tperm, d_keys,
-                           p.d_px, p.d_py, p.d_perm);
     }
+    // entries per tile (the cursor array is free again), scanned into the plan's tile_start
+    hipLaunchKernelGGL(k_tile_entries, dim3((unsigned)p.ntiles), dim3(kOrderThreads),
+                       sizeof(int32_t) * (size_t)p.tile_x * p.tile_y, st, a, d_pstart, tpx, tpy, d_cursor);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cursor, p.ntiles, p.d_tile_start, d_cursor);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_sort_order(psht_plan_s &p, int32_t *d_keys, const int32_t *d_pstart, const double *tpx,
+                                   const double *tpy, const int32_t *tperm, hipStream_t st) {
+    if (p.npts == 0) return hipSuccess;
+    const SortArgs a = sort_args(p);
+    // keys are no longer needed: they hold the per-point ranks from here on
+    hipLaunchKernelGGL(k_tile_order, dim3((unsigned)p.ntiles), dim3(kOrderThreads),
+                       tile_order_lds_bytes(p.tile_x, p.tile_y), st, a, d_pstart, p.d_tile_start, tpx, tpy, tperm,
+                       d_keys, p.d_px, p.d_py, p.d_perm);
     return hipGetLastError();
 }
 

@@ -126,7 +126,8 @@ struct psht_plan_s {
     int tile_x = 16, tile_y = 32, ntx = 0, nty = 0, ntiles = 0;
     double *d_px = nullptr, *d_py = nullptr;
     int32_t *d_perm = nullptr;
-    int32_t *d_tile_start = nullptr;  // ntiles + 1
+    int32_t *d_tile_start = nullptr;  // ntiles + 1, in entries (2 per slot)
+    int64_t n_entries = 0;            // slot entries of all tiles (points + dummies)
     // workspace layout (bytes, per map)
     size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_Q = 0, ws_per_map = 0;
     size_t resident = 0;
@@ -168,8 +169,16 @@ hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, co
 // Plan-time point kernels.
 hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n, double *d_stats,
                               hipStream_t st);
-hipError_t launch_point_sort(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
-                             int32_t *d_cursor, double *tpx, double *tpy, int32_t *tperm, hipStream_t st);
+// Bucket sort of the points into NUFFT tiles in two launches: the first
+// counts and scatters the points into tiles (tpx, tpy, tperm, tile ranges
+// d_pstart) and writes p.d_tile_start in entries (2 per slot, see k_nufft.hip);
+// the caller then sizes p.d_px/d_py/d_perm to p.d_tile_start[ntiles] entries
+// and the second launch writes the slot layout.
+hipError_t launch_point_sort_count(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
+                                   int32_t *d_cursor, int32_t *d_pstart, double *tpx, double *tpy, int32_t *tperm,
+                                   hipStream_t st);
+hipError_t launch_point_sort_order(psht_plan_s &p, int32_t *d_keys, const int32_t *d_pstart, const double *tpx,
+                                   const double *tpy, const int32_t *tperm, hipStream_t st);
 
 // Rings per lane of the Legendre kernels (a work item covers 64 x this many rings).
 int leg_rings_per_lane();
