@@ -234,6 +234,17 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         p.n_leg_items = (int)items.size();
         p.leg_rings_per_item = chunk;
         if (!upload(p, p.d_leg_items, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
+        const int chunk_adj = 64 * psht::leg_adj_rings_per_lane();
+        p.leg_rings_per_item_adj = chunk_adj;
+        if (chunk_adj == chunk) {
+            p.d_leg_items_adj = p.d_leg_items;
+            p.n_leg_items_adj = p.n_leg_items;
+        } else {
+            build_items(chunk_adj, items);
+            p.n_leg_items_adj = (int)items.size();
+            if (!upload(p, p.d_leg_items_adj, items, st))
+                return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
+        }
         build_items(64, items);
         p.n_leg_items64 = (int)items.size();
         if (!upload(p, p.d_leg_items64, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");

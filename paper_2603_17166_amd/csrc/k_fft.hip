@@ -135,8 +135,10 @@ template <typename C, int R> __device__ inline void dft(C *v, int sign) {
     }
 }
 
-// Threads of a workgroup transforming up to MAXN points.
-__host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2048 ? 256 : 512; }
+// Threads of a workgroup transforming up to MAXN points.  The longest tier
+// holds up to 128 KB of LDS, one workgroup per CU: 1024 threads give each
+// SIMD four waves to hide the LDS and twiddle latency.
+__host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2048 ? 256 : (maxn <= 4096 ? 512 : 1024); }
 
 // One Stockham pass of radix R on buf[0..n) with stride Ns.  Every thread
 // holds NB butterflies in registers; NB follows from the largest transform
@@ -164,8 +166,16 @@ __device__ void fft_pass(typename CT<T>::type *buf, int n, int Ns, int sign, con
         int b = threadIdx.x + i * NT;
         if (b < nb) {
             int k = b % Ns;
+            // twiddles w^r (r = 1..R-1) as powers of the one table entry w:
+            // one load per butterfly instead of R - 1 scattered ones
+            const C w1 = twiddle<C>(tw, k * tws, sign);
+            C wr = w1;
+            v[i][1] = cmul(v[i][1], w1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twiddle<C>(tw, r * k * tws, sign));
+            for (int r = 2; r < R; ++r) {
+                wr = cmul(wr, w1);
+                v[i][r] = cmul(v[i][r], wr);
+            }
             dft<C, R>(v[i], sign);
             int d = (b - k) * R + k;
 #pragma unroll

@@ -643,6 +643,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
 }
 
+// Arguments over the synthesis work list (64 R rings per item); the adjoint
+// replaces items and nitems by its own list.
 template <int R>
 static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out, double *F) {
     const Geometry &g = p.g;
@@ -669,13 +671,21 @@ static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out
     return a;
 }
 
-// Rings per lane: 2 unless PSHT_LEG_R (1, 2, 4 or 8) overrides it for tuning runs.
+static int rings_knob(const char *name, int dflt) {
+    const char *e = getenv(name);
+    const int v = e ? atoi(e) : dflt;
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : dflt;
+}
+
+// Rings per lane: 2 for both directions unless PSHT_LEG_R (synthesis) or
+// PSHT_LEG_RA (adjoint), each 1, 2, 4 or 8, overrides it for tuning runs.
 int leg_rings_per_lane() {
-    static int r = [] {
-        const char *e = getenv("PSHT_LEG_R");
-        int v = e ? atoi(e) : 2;
-        return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 2;
-    }();
+    static const int r = rings_knob("PSHT_LEG_R", 2);
+    return r;
+}
+
+int leg_adj_rings_per_lane() {
+    static const int r = rings_knob("PSHT_LEG_RA", 2);
     return r;
 }
 
@@ -707,8 +717,10 @@ static int leg_adj_chunk() {
 template <int R>
 static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
     LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
+    a.items = p.d_leg_items_adj;
+    a.nitems = p.n_leg_items_adj;
     a.mscale = mscale;
-    dim3 grid(p.n_leg_items), block(64);
+    dim3 grid(p.n_leg_items_adj), block(64);
     if (leg_adj_chunk() == 4) {
         if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 4>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_leg_adjoint<R, false, 4>), grid, block, 0, st, a);
@@ -764,8 +776,8 @@ hipError_t launch_leg_synth_batch(const psht_plan_s &p, int nb, const void *alm0
 }
 
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
-    if (p.n_leg_items == 0) return hipSuccess;
-    switch (p.leg_rings_per_item / 64) {
+    if (p.n_leg_items_adj == 0) return hipSuccess;
+    switch (p.leg_rings_per_item_adj / 64) {
         case 1: leg_adjoint_r<1>(p, F, alm, mscale, st); break;
         case 2: leg_adjoint_r<2>(p, F, alm, mscale, st); break;
         case 8: leg_adjoint_r<8>(p, F, alm, mscale, st); break;

@@ -37,6 +37,13 @@ struct NufftArgs {
 
 __device__ __host__ inline int stencil_origin(double X, int W) { return (int)ceil(X - 0.5 * W); }
 
+// Row stride (in elements) of a tile's subgrid in LDS: odd, so that the
+// stencil origins (li, lj) of the slots a wave handles in one instruction
+// fall in distinct LDS banks when their classes (li * stride + lj) mod 32
+// are distinct, which is how k_tile_order lays the slots out.
+__device__ __host__ inline int tile_row_stride(int tile_y, int W) { return (tile_y + W - 1) | 1; }
+constexpr int kBankClasses = 32;
+
 __device__ inline double es_kernel(double z, double beta) {
     double t = fmax(0.0, 1.0 - z * z);
     return exp(beta * (sqrt(t) - 1.0));
@@ -97,7 +104,7 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
     const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
     if (p0 == p1) return;
     const int tx = t / a.nty, ty = t - tx * a.nty;
-    const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1;
+    const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1, SYP = tile_row_stride(a.tile_y, W);
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
     for (int e = threadIdx.x; e < SX * SY; e += kTileThreads) {
         const int i = e / SY, j = e - i * SY;
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         C v;
         v.x = v.y = (T)0;
         if (row < a.rows_used) v = U[(int64_t)row * a.Nphi + col];
-        S[e] = v;
+        S[i * SYP + j] = v;
     }
     __syncthreads();
     // one entry per thread; the two entries of a slot (same cell) sit in
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         double accr = 0.0, acci = 0.0;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            const C *Srow = S + (li + i) * SY + lj;
+            const C *Srow = S + (li + i) * SYP + lj;
             double rr = 0.0, ri = 0.0;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
@@ -146,8 +153,9 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
     }
 }
 
+// (at most 128 VGPRs: four waves per SIMD measured faster than three)
 template <typename T, int W>
-__global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const typename CplxT<T>::type *map,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spread(NufftArgs a, const typename CplxT<T>::type *map,
                                                          T *U) {
     typedef typename CplxT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -156,7 +164,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
     if (p0 == p1) return;
     const int tx = t / a.nty, ty = t - tx * a.nty;
     const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1;
-    const int SYP = SY | 1;  // odd row stride spreads neighbouring rows over the LDS banks
+    const int SYP = tile_row_stride(a.tile_y, W);
     // Separate real and imaginary planes, accumulated in double for both map
     // precisions: the FP64 LDS atomic add is a native fast path on gfx950,
     // while FP32 LDS atomic adds measured an order of magnitude slower.
@@ -236,7 +244,7 @@ template <typename T, int W>
 static hipError_t launch_interp_w(const psht_plan_s &p, const void *U, void *map, hipStream_t st) {
     typedef typename CplxT<T>::type C;
     NufftArgs a = nufft_args(p);
-    size_t lds = (size_t)(p.tile_x + W - 1) * (p.tile_y + W - 1) * sizeof(C);
+    size_t lds = (size_t)(p.tile_x + W - 1) * tile_row_stride(p.tile_y, W) * sizeof(C);
     hipLaunchKernelGGL((k_interp<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
                        static_cast<const C *>(U), static_cast<C *>(map));
     return hipGetLastError();
@@ -246,7 +254,7 @@ template <typename T, int W>
 static hipError_t launch_spread_w(const psht_plan_s &p, const void *map, void *U, hipStream_t st) {
     typedef typename CplxT<T>::type C;
     NufftArgs a = nufft_args(p);
-    size_t lds = (size_t)(p.tile_x + W - 1) * ((p.tile_y + W - 1) | 1) * 2 * sizeof(double);
+    size_t lds = (size_t)(p.tile_x + W - 1) * tile_row_stride(p.tile_y, W) * 2 * sizeof(double);
     hipLaunchKernelGGL((k_spread<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
                        static_cast<const C *>(map), static_cast<T *>(U));
     return hipGetLastError();
@@ -433,13 +441,12 @@ __global__ void k_point_scatter(SortArgs a, const double *theta, const double *p
 // second entry is a dummy with perm = -1 when a cell has an odd count), so a
 // thread spreading a slot adds both points' contributions in registers before
 // each LDS update, and a thread interpolating a slot reads every subgrid value
-// once for both.  Points are ranked within their cell (0, 1, 2, ...), slot
-// rank = rank / 2, and slots are laid out rank by rank, each rank level in
-// row-major cell order: consecutive lanes of a wave then take slots of
-// distinct, mostly adjacent cells, so the W x W stencils they update in one
-// instruction hit distinct LDS addresses.  Slot ranks from kRankLevels - 1 up
-// share the last level, which bounds the work for cells with very many points.
-constexpr int kRankLevels = 16;
+// once for both.  A cell (li, lj) has the bank class (li * stride + lj) mod 32
+// of its subgrid address (tile_row_stride).  Within a class the slots are
+// numbered cell by cell in row-major order (class rank), and the tile's slots
+// are laid out by class rank, then class: while all classes still have slots,
+// every 32 consecutive slots cover the 32 classes once, so the W x W stencils
+// that consecutive lanes update in one instruction fall in distinct LDS banks.
 constexpr int kOrderThreads = 256;
 
 __device__ inline int cell_in_tile(const SortArgs &a, double X, double Y, int r0, int c0) {
@@ -449,32 +456,6 @@ __device__ inline int cell_in_tile(const SortArgs &a, double X, double Y, int r0
     const int li = min(max(a0 - a.row_lo - r0, 0), a.tile_x - 1);
     const int lj = min(max(b0m - c0, 0), a.tile_y - 1);
     return li * a.tile_y + lj;
-}
-
-// Exclusive block scan of v[0..n) in place (kOrderThreads threads, part[] of
-// kOrderThreads ints); returns the total.  Every thread must call it.
-__device__ inline int block_exclusive_scan(int32_t *v, int n, int32_t *part) {
-    const int per = (n + kOrderThreads - 1) / kOrderThreads;
-    const int b = threadIdx.x * per, e = min(n, b + per);
-    int32_t s = 0;
-    for (int i = b; i < e; ++i) s += v[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < kOrderThreads; off <<= 1) {
-        const int32_t u = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += u;
-        __syncthreads();
-    }
-    int32_t run = part[threadIdx.x] - s;
-    for (int i = b; i < e; ++i) {
-        const int32_t c = v[i];
-        v[i] = run;
-        run += c;
-    }
-    const int32_t total = part[kOrderThreads - 1];
-    __syncthreads();
-    return total;
 }
 
 // Entries (2 per slot) of every tile: sum over cells of 2 ceil(count / 2).
@@ -514,56 +495,60 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const 
                                                               int32_t *rank, double *px, double *py, int32_t *perm) {
     extern __shared__ int32_t osm[];
     const int C = a.tile_x * a.tile_y;
-    int32_t *cnt = osm, *pos = osm + C, *part = osm + 2 * C;
-    __shared__ int32_t s_kmax;
+    int32_t *cnt = osm, *first = osm + C;  // points per cell; class rank of the cell's first slot
+    __shared__ int32_t nk[kBankClasses];   // slots per class
     const int t = blockIdx.x;
     const int p0 = pstart[t], p1 = pstart[t + 1];
     if (p0 == p1) return;
     const int e0 = estart[t];
     const int r0 = (t / a.nty) * a.tile_x, c0 = (t % a.nty) * a.tile_y;
+    const int stride = tile_row_stride(a.tile_y, a.W);
     for (int c = threadIdx.x; c < C; c += kOrderThreads) cnt[c] = 0;
-    if (threadIdx.x == 0) s_kmax = 0;
     __syncthreads();
-    for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
-        const int r = atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
-        rank[p] = r;
-        atomicMax(&s_kmax, r / 2 + 1);
-    }
+    for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads)
+        rank[p] = atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
     __syncthreads();
-    const int levels = min(s_kmax, kRankLevels);
-    int base = 0;  // slots before this level
-    for (int lev = 0; lev < levels; ++lev) {
-        const bool last = lev == kRankLevels - 1;
-        // slots of this level per cell: 1, or every remaining slot on the last level
-        for (int c = threadIdx.x; c < C; c += kOrderThreads) {
-            const int sl = (cnt[c] + 1) / 2;  // slots of the cell
-            pos[c] = sl > lev ? (last ? sl - lev : 1) : 0;
-        }
-        __syncthreads();
-        const int n_lev = block_exclusive_scan(pos, C, part);
-        for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
-            const int r = rank[p], sr = r / 2;
-            if (sr < lev || (sr > lev && !last)) continue;
-            const int cell = cell_in_tile(a, tpx[p], tpy[p], r0, c0);
-            const int slot = base + pos[cell] + (last ? sr - lev : 0);
-            const int dst = e0 + 2 * slot + (r & 1);
-            px[dst] = tpx[p];
-            py[dst] = tpy[p];
-            perm[dst] = tperm[p];
-            if (r == cnt[cell] - 1 && !(r & 1)) {  // odd cell: the slot's second entry is a dummy
-                px[dst + 1] = tpx[p];
-                py[dst + 1] = tpy[p];
-                perm[dst + 1] = -1;
+    // one thread per class walks its cells in row-major order
+    if (threadIdx.x < kBankClasses) {
+        const int k = threadIdx.x;
+        int run = 0;
+        for (int li = 0; li < a.tile_x; ++li) {
+            const int lj0 = ((k - li * stride) % kBankClasses + kBankClasses) % kBankClasses;
+            for (int lj = lj0; lj < a.tile_y; lj += kBankClasses) {
+                const int c = li * a.tile_y + lj;
+                first[c] = run;
+                run += (cnt[c] + 1) / 2;
             }
         }
-        base += n_lev;
-        __syncthreads();
+        nk[k] = run;
+    }
+    __syncthreads();
+    for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
+        const int r = rank[p];
+        const int cell = cell_in_tile(a, tpx[p], tpy[p], r0, c0);
+        const int li = cell / a.tile_y, lj = cell - li * a.tile_y;
+        const int k = (li * stride + lj) % kBankClasses;
+        const int R = first[cell] + r / 2;  // class rank of the point's slot
+        // slots before (R, k): every slot of class rank < R, and those of rank R in classes < k
+        int slot = 0;
+#pragma unroll 8
+        for (int k2 = 0; k2 < kBankClasses; ++k2) {
+            const int n2 = nk[k2];
+            slot += min(n2, R) + ((k2 < k && n2 > R) ? 1 : 0);
+        }
+        const int dst = e0 + 2 * slot + (r & 1);
+        px[dst] = tpx[p];
+        py[dst] = tpy[p];
+        perm[dst] = tperm[p];
+        if (r == cnt[cell] - 1 && !(r & 1)) {  // odd cell: the slot's second entry is a dummy
+            px[dst + 1] = tpx[p];
+            py[dst + 1] = tpy[p];
+            perm[dst + 1] = -1;
+        }
     }
 }
 
-size_t tile_order_lds_bytes(int tile_x, int tile_y) {
-    return sizeof(int32_t) * (2 * (size_t)tile_x * tile_y + kOrderThreads);
-}
+size_t tile_order_lds_bytes(int tile_x, int tile_y) { return sizeof(int32_t) * 2 * (size_t)tile_x * tile_y; }
 
 static SortArgs sort_args(const psht_plan_s &p) {
     SortArgs a;

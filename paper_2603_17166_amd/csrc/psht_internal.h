@@ -114,6 +114,9 @@ struct psht_plan_s {
     psht::LegItem *d_leg_items = nullptr;
     int n_leg_items = 0;
     int leg_rings_per_item = 0;
+    psht::LegItem *d_leg_items_adj = nullptr;  // adjoint list (its own rings per lane; may alias d_leg_items)
+    int n_leg_items_adj = 0;
+    int leg_rings_per_item_adj = 0;
     psht::LegItem *d_leg_items64 = nullptr;  // 64-ring chunks (batched-maps kernel)
     int n_leg_items64 = 0;
     std::shared_ptr<psht::LegTable> leg;
@@ -180,8 +183,10 @@ hipError_t launch_point_sort_count(psht_plan_s &p, const double *theta, const do
 hipError_t launch_point_sort_order(psht_plan_s &p, int32_t *d_keys, const int32_t *d_pstart, const double *tpx,
                                    const double *tpy, const int32_t *tperm, hipStream_t st);
 
-// Rings per lane of the Legendre kernels (a work item covers 64 x this many rings).
+// Rings per lane of the Legendre synthesis and adjoint kernels (a work item
+// covers 64 x this many rings).
 int leg_rings_per_lane();
+int leg_adj_rings_per_lane();
 
 // Largest FFT length one workgroup transforms in LDS.
 constexpr int kFftMaxLds64 = 8192;

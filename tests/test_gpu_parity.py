@@ -192,6 +192,27 @@ def test_pole_and_wrapped_longitudes():
     assert rel_l2(f, ref) <= 10 * eps
 
 
+def test_clustered_points():
+    """Many points in one NUFFT cell (an odd count, duplicates included) next to
+    a sparse background: the tile layout then has one bank class with
+    thousands of slots and classes with none."""
+    lmax, spin, eps = 96, 2, 1e-10
+    th0, ph0 = syn.uniform_cap(600, 15 * DEG, 8250)
+    g = syn.rng(8260)
+    th1 = 0.1 + 1e-7 * g.random(2001)
+    ph1 = 1.3 + 1e-7 * g.random(2001)
+    th1[:300] = th1[0]
+    ph1[:300] = ph1[0]
+    th, ph = np.concatenate([th0, th1]), np.concatenate([ph0, ph1])
+    a = syn.gaussian_alm(lmax, spin, 8270)
+    plan = Plan(th, ph, lmax, spin, eps)
+    f = plan.synth(dev(a)).cpu().numpy()
+    assert rel_l2(f, oracle.synth(a, th, ph, lmax, spin)) <= 10 * eps
+    y = syn.gaussian_map(th.shape[0], 8280)
+    at = plan.adjoint(dev(y)).cpu().numpy()
+    assert alm_rel(at, oracle.adjoint(y, th, ph, lmax, spin), lmax) <= 10 * eps
+
+
 def test_empty_and_single_point():
     lmax, spin = 32, 0
     a = dev(syn.gaussian_alm(lmax, spin, 8300))
