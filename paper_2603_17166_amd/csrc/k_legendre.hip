@@ -164,10 +164,9 @@ __device__ inline double4 stage_entry(const double4 *T4, const double4 *Q4, int 
 
 // Steps t in [t0, t1) of a staged chunk starting at l = c (t1 - t0 <= 8):
 // accumulate lambda_l into the ring sums, then advance the recurrence.
-template <int R, bool SPIN, bool MASKED>
+template <int R, bool SPIN>
 __device__ inline void synth_steps(LegState<R, SPIN> &S, double *fpr, double *fpi, double *fmr, double *fmi,
-                                   const double4 *sT, const double4 *sQ, int t0, int t1, int c, int lmax,
-                                   const double *cp, const double *cm) {
+                                   const double4 *sT, const double4 *sQ, int t0, int t1, int c, int lmax) {
 #pragma unroll 2
     for (int u = 0; u < 8; ++u) {
         const int t = t0 + u;
@@ -175,11 +174,7 @@ __device__ inline void synth_steps(LegState<R, SPIN> &S, double *fpr, double *fp
             const double4 q = sQ[t];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
-                if (MASKED) {
-                    vp *= cp[r];
-                    vm *= cm[r];
-                }
+                const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
                 fpr[r] = fma(q.x, vp, fpr[r]);
                 fpi[r] = fma(q.y, vp, fpi[r]);
                 fmr[r] = fma(q.z, vm, fmr[r]);
@@ -190,11 +185,79 @@ __device__ inline void synth_steps(LegState<R, SPIN> &S, double *fpr, double *fp
     }
 }
 
-template <int R, bool SPIN> __device__ inline void leg_masks(const LegState<R, SPIN> &S, double *cp, double *cm) {
+// True when some active ring of the wave holds an unscaled value; otherwise
+// every term of the current steps is exactly zero and only the recurrence
+// has to run.
+template <int R, bool SPIN> __device__ inline bool leg_live(const LegState<R, SPIN> &S) {
+    bool lv = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lv |= S.act[r] && (S.kp[r] == 0 || (SPIN && S.km[r] == 0));
+    return __any(lv);
+}
+
+// Recurrence alone over the steps t in [t0, t1) of a staged chunk; FULL: the
+// NS steps from t0 all advance (no guards).
+template <int R, bool SPIN, bool FULL, int NS>
+__device__ inline void advance_steps(LegState<R, SPIN> &S, const double4 *sT, int t0, int t1, int c, int lmax) {
+    if (FULL) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) leg_advance<R, SPIN>(S, sT[t0 + u]);
+    } else {
+        for (int t = t0; t < t1; ++t)
+            if (c + t < lmax) leg_advance<R, SPIN>(S, sT[t]);
+    }
+}
+
+// Steps b..b+7 of a staged chunk when all eight advance: fully unrolled, no guards.
+template <int R, bool SPIN>
+__device__ inline void synth_steps8(LegState<R, SPIN> &S, double *fpr, double *fpi, double *fmr, double *fmi,
+                                    const double4 *sT, const double4 *sQ, int b) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double4 q = sQ[b + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
+            fpr[r] = fma(q.x, vp, fpr[r]);
+            fpi[r] = fma(q.y, vp, fpi[r]);
+            fmr[r] = fma(q.z, vm, fmr[r]);
+            fmi[r] = fma(q.w, vm, fmi[r]);
+        }
+        leg_advance<R, SPIN>(S, sT[b + u]);
+    }
+}
+
+// Scaled values in the synthesis.  The sums of a ring take its stored values
+// unmasked; while the ring's scale k is negative those terms are not its true
+// (negligible, below 2^-312) ones, so the sums restart when k reaches 0 and
+// are cleared at the end if it never does (synth_clear_scaled).
+template <int R, bool SPIN>
+__device__ inline void synth_renorm(LegState<R, SPIN> &S, double *fpr, double *fpi, double *fmr, double *fmi) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        cp[r] = S.kp[r] == 0 ? 1.0 : 0.0;
-        cm[r] = (SPIN ? S.km[r] : S.kp[r]) == 0 ? 1.0 : 0.0;
+        const int kp0 = S.kp[r];
+        rescale_sel(S.up[r], S.upp[r], S.kp[r]);
+        const bool rp = kp0 < 0 && S.kp[r] == 0;
+        fpr[r] = rp ? 0.0 : fpr[r];
+        fpi[r] = rp ? 0.0 : fpi[r];
+        bool rm = rp;
+        if (SPIN) {
+            const int km0 = S.km[r];
+            rescale_sel(S.um[r], S.ump[r], S.km[r]);
+            rm = km0 < 0 && S.km[r] == 0;
+        }
+        fmr[r] = rm ? 0.0 : fmr[r];
+        fmi[r] = rm ? 0.0 : fmi[r];
+    }
+}
+
+template <int R, bool SPIN>
+__device__ inline void synth_clear_scaled(const LegState<R, SPIN> &S, double *fpr, double *fpi, double *fmr,
+                                          double *fmi) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (S.kp[r] < 0) fpr[r] = fpi[r] = 0.0;
+        if ((SPIN ? S.km[r] : S.kp[r]) < 0) fmr[r] = fmi[r] = 0.0;
     }
 }
 
@@ -277,15 +340,19 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
             }
         } else for (int b = 0; b < n; b += 8) {
             const int e = min(b + 8, n);
-            if (scaled) {
-                // some lane still below the double range: masked accumulation, then renormalise
-                double cp[R], cm[R];
-                leg_masks<R, SPIN>(S, cp, cm);
-                synth_steps<R, SPIN, true>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lmax, cp, cm);
-                leg_renorm<R, SPIN>(S);
-                scaled = leg_any_scaled<R, SPIN>(S);
+            const bool full = c + b + 8 <= lmax;  // all eight steps exist and advance
+            if (scaled && !leg_live<R, SPIN>(S)) {
+                // no active ring in the double range yet: recurrence only
+                if (full) advance_steps<R, SPIN, true, 8>(S, sT, b, e, c, lmax);
+                else advance_steps<R, SPIN, false, 8>(S, sT, b, e, c, lmax);
+            } else if (full) {
+                synth_steps8<R, SPIN>(S, fpr, fpi, fmr, fmi, sT, sQ, b);
             } else {
-                synth_steps<R, SPIN, false>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lmax, nullptr, nullptr);
+                synth_steps<R, SPIN>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lmax);
+            }
+            if (scaled) {
+                synth_renorm<R, SPIN>(S, fpr, fpi, fmr, fmi);
+                scaled = leg_any_scaled<R, SPIN>(S);
             }
         }
         if (has_next) sbuf[slot ^ 1][lane >> 5][lane & 31] = nv;
@@ -293,6 +360,7 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
         slot ^= 1;
     }
 
+    synth_clear_scaled<R, SPIN>(S, fpr, fpi, fmr, fmi);
     const double sgn_neg = (s & 1) ? 1.0 : -1.0;  // -(-1)^s
     double2 *Fp = reinterpret_cast<double2 *>(a.F) + (int64_t)(a.mmax + m) * a.nring;
     double2 *Fm = reinterpret_cast<double2 *>(a.F) + (int64_t)(a.mmax - m) * a.nring;
@@ -326,12 +394,122 @@ __device__ inline void swap16(double &x, double &y) {
     y = __hiloint2double(hi[1], lo[1]);
 }
 
+// Fold of one l-step's four lane sums c0..c3 (Re and Im of the + and - sums)
+// into the transposed reduction, as soon as they are computed: a 32-lane swap
+// keeps component c + 2 bit5(i) in lane i, summed over lanes i and i ^ 32; the
+// two steps u and u + 1 then share a 16-lane swap that keeps step
+// u + bit4(i), summed over {i, i ^ 16, i ^ 32, i ^ 48}.  After CH steps w
+// holds CH values per lane: w[2 (u / 2) + (c & 1)].
+template <int CH>
+__device__ inline void adj_fold(int u, double c0, double c1, double c2, double c3, double *w) {
+    swap32(c0, c2);
+    c0 += c2;
+    swap32(c1, c3);
+    c1 += c3;
+    const int p = u >> 1;
+    if ((u & 1) == 0) {
+        w[2 * p] = c0;
+        w[2 * p + 1] = c1;
+    } else {
+        swap16(w[2 * p], c0);
+        w[2 * p] += c0;
+        swap16(w[2 * p + 1], c1);
+        w[2 * p + 1] += c1;
+    }
+}
+
+// CH steps from b of a staged chunk, all advancing: partial sums of the
+// lane's rings folded into w; independent work first (step coefficients,
+// partial sums), the dependent recurrence updates last.
+template <int R, bool SPIN, int CH>
+__device__ inline void adj_block(LegState<R, SPIN> &S, const double4 *sT, int b, const double *fpr,
+                                 const double *fpi, const double *fmr, const double *fmi, double *w) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const double4 tc = sT[b + u];
+        double cpl[R], cmi[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cpl[r] = fma(tc.x, S.y[r], tc.y);
+            if (SPIN) cmi[r] = fma(tc.x, S.y[r], tc.z);
+        }
+        double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
+            pa_r = fma(vp, fpr[r], pa_r);
+            pa_i = fma(vp, fpi[r], pa_i);
+            pb_r = fma(vm, fmr[r], pb_r);
+            pb_i = fma(vm, fmi[r], pb_i);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double np = fma(cpl[r], S.up[r], -S.upp[r]);
+            S.upp[r] = S.up[r];
+            S.up[r] = np;
+            if (SPIN) {
+                const double nm = fma(cmi[r], S.um[r], -S.ump[r]);
+                S.ump[r] = S.um[r];
+                S.um[r] = nm;
+            }
+        }
+        adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w);
+    }
+}
+
+// Scaled values in the adjoint.  A ring's map values enter its partial sums
+// only while its scale k is 0: they are held at zero while k < 0 and loaded
+// when k reaches 0, so the stored (scaled) values need no mask.
+template <int R, bool SPIN>
+__device__ inline void adj_load_f(const LegState<R, SPIN> &S, const double2 *Fp, const double2 *Fm, int j0,
+                                  int lane, double *fpr, double *fpi, double *fmr, double *fmi) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
+        if (S.act[r]) {
+            const int j = j0 + r * 64 + lane;
+            if (S.kp[r] == 0) {
+                const double2 vp = Fp[j];
+                fpr[r] = vp.x;
+                fpi[r] = vp.y;
+            }
+            if ((SPIN ? S.km[r] : S.kp[r]) == 0) {
+                const double2 vm = Fm[j];
+                fmr[r] = vm.x;
+                fmi[r] = -vm.y;  // conj F'(-m); for m = 0 the same column
+            }
+        }
+    }
+}
+
+template <int R, bool SPIN>
+__device__ inline void adj_renorm(LegState<R, SPIN> &S, const double2 *Fp, const double2 *Fm, int j0, int lane,
+                                  double *fpr, double *fpi, double *fmr, double *fmi) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int kp0 = S.kp[r], km0 = SPIN ? S.km[r] : 0;
+        rescale_sel(S.up[r], S.upp[r], S.kp[r]);
+        if (SPIN) rescale_sel(S.um[r], S.ump[r], S.km[r]);
+        const int j = j0 + r * 64 + lane;
+        if (kp0 < 0 && S.kp[r] == 0) {
+            const double2 vp = Fp[j];
+            fpr[r] = vp.x;
+            fpi[r] = vp.y;
+        }
+        if (SPIN ? (km0 < 0 && S.km[r] == 0) : (kp0 < 0 && S.kp[r] == 0)) {
+            const double2 vm = Fm[j];
+            fmr[r] = vm.x;
+            fmi[r] = -vm.y;
+        }
+    }
+}
+
 // CH: values of l per transposed reduction (4 or 8).
 template <int R, bool SPIN, int CH>
 __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
-    constexpr int kAdjChunk = CH, NV = 4 * CH;  // NV partial sums per lane per block
+    constexpr int kAdjChunk = CH, NV = 4 * CH;  // NV partial sums per block of CH steps
     __shared__ double4 sbuf[2][kStage];
-    __shared__ double red[4][NV / 4][17];
+    __shared__ double red[4][CH][17];
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
@@ -349,18 +527,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     double fpr[R], fpi[R], fmr[R], fmi[R];
     const double2 *Fp = reinterpret_cast<const double2 *>(a.F) + (int64_t)(a.mmax + m) * a.nring;
     const double2 *Fm = reinterpret_cast<const double2 *>(a.F) + (int64_t)(a.mmax - m) * a.nring;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
-        if (S.act[r]) {
-            const int j = it.jb + r * 64 + lane;
-            const double2 vp = Fp[j], vm = Fm[j];
-            fpr[r] = vp.x;
-            fpi[r] = vp.y;
-            fmr[r] = vm.x;
-            fmi[r] = -vm.y;  // conj F'(-m); for m = 0 the same column
-        }
-    }
+    adj_load_f<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
     const double sgn_s = (s & 1) ? -1.0 : 1.0;
     const int row = lane >> 4, col = lane & 15;
     bool scaled = leg_any_scaled<R, SPIN>(S);
@@ -374,48 +541,21 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
         const double4 *sT = sbuf[slot];
         const int n = min(kStage, lmax + 1 - c);
         for (int b = 0; b < n; b += kAdjChunk) {
-            // per-lane partial sums over the lane's rings, 4 components per l
-            double v[4 * kAdjChunk];
-            double cp[R], cm[R];
-            if (scaled) leg_masks<R, SPIN>(S, cp, cm);
-            const bool plain = !scaled && (c + b + kAdjChunk <= lmax);  // every step advances
-            if (plain) {
-#pragma unroll
-                for (int u = 0; u < kAdjChunk; ++u) {
-                    // independent work first (step coefficients, partial sums),
-                    // the dependent recurrence updates last
-                    const double4 tc = sT[b + u];
-                    double cpl[R], cmi[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        cpl[r] = fma(tc.x, S.y[r], tc.y);
-                        if (SPIN) cmi[r] = fma(tc.x, S.y[r], tc.z);
-                    }
-                    double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
-                        pa_r = fma(vp, fpr[r], pa_r);
-                        pa_i = fma(vp, fpi[r], pa_i);
-                        pb_r = fma(vm, fmr[r], pb_r);
-                        pb_i = fma(vm, fmi[r], pb_i);
-                    }
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const double np = fma(cpl[r], S.up[r], -S.upp[r]);
-                        S.upp[r] = S.up[r];
-                        S.up[r] = np;
-                        if (SPIN) {
-                            const double nm = fma(cmi[r], S.um[r], -S.ump[r]);
-                            S.ump[r] = S.um[r];
-                            S.um[r] = nm;
-                        }
-                    }
-                    v[4 * u + 0] = pa_r;
-                    v[4 * u + 1] = pa_i;
-                    v[4 * u + 2] = pb_r;
-                    v[4 * u + 3] = pb_i;
-                }
+            // per-lane partial sums over the lane's rings, 4 components per l,
+            // folded step by step (adj_fold)
+            double w[kAdjChunk];
+            const bool full = c + b + kAdjChunk <= lmax;  // every step of the block exists and advances
+            if (scaled && !leg_live<R, SPIN>(S)) {
+                // every active lane below the double range: all partial sums
+                // vanish, so the block needs neither sums nor reduction
+                if (full) advance_steps<R, SPIN, true, kAdjChunk>(S, sT, b, n, c, lmax);
+                else advance_steps<R, SPIN, false, kAdjChunk>(S, sT, b, min(b + kAdjChunk, n), c, lmax);
+                adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
+                scaled = leg_any_scaled<R, SPIN>(S);
+                continue;
+            }
+            if (full) {
+                adj_block<R, SPIN, CH>(S, sT, b, fpr, fpi, fmr, fmi, w);
             } else
 #pragma unroll
             for (int u = 0; u < kAdjChunk; ++u) {
@@ -424,11 +564,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                 if (t < n) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
-                        if (scaled) {
-                            vp *= cp[r];
-                            vm *= cm[r];
-                        }
+                        const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
                         pa_r = fma(vp, fpr[r], pa_r);
                         pa_i = fma(vp, fpi[r], pa_i);
                         pb_r = fma(vm, fmr[r], pb_r);
@@ -436,43 +572,28 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                     }
                     if (c + t < lmax) leg_advance<R, SPIN>(S, sT[t]);
                 }
-                v[4 * u + 0] = pa_r;
-                v[4 * u + 1] = pa_i;
-                v[4 * u + 2] = pb_r;
-                v[4 * u + 3] = pb_i;
+                adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w);
             }
             if (scaled) {
-                leg_renorm<R, SPIN>(S);
+                adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
                 scaled = leg_any_scaled<R, SPIN>(S);
             }
-            // Transposed reduction over the 64 lanes: two permlane stages leave each
-            // lane with NV/4 values summed over lanes {i, i^16, i^32, i^48}; value k
-            // of lane i then stands for index k + (NV/4) bit4(i) + (NV/2) bit5(i) of v.
+            // The remaining sum over the 16 lanes of each row q = lane >> 4 goes
+            // through LDS.  Output o = 4 u + c (step u, component c) sits in row
+            // q = 2 (c >> 1) + (u & 1), value k = 2 (u >> 1) + (c & 1); 64/NV lanes
+            // share an output and each sums 16 NV/64 columns.
 #pragma unroll
-            for (int k = 0; k < NV / 2; ++k) {
-                swap32(v[k], v[k + NV / 2]);
-                v[k] += v[k + NV / 2];
-            }
-#pragma unroll
-            for (int k = 0; k < NV / 4; ++k) {
-                swap16(v[k], v[k + NV / 4]);
-                v[k] += v[k + NV / 4];
-            }
-#pragma unroll
-            for (int k = 0; k < NV / 4; ++k) red[row][k][col] = v[k];
+            for (int k = 0; k < kAdjChunk; ++k) red[row][k][col] = w[k];
             __syncthreads();
-            // output o = (row q, value k), o = q NV/4 + k, is the sum over the 16
-            // lanes of row q; 64/NV lanes share an output and each sums NV/4 of them
             constexpr int PARTS = 64 / NV, PER = 16 / PARTS;
             const int o = lane & (NV - 1), hh = lane / NV;
-            const int q = o / (NV / 4), k = o % (NV / 4);
+            const int q = 2 * ((o & 3) >> 1) + ((o >> 2) & 1), k = 2 * (o >> 3) + (o & 1);
             double sum = 0.0;
 #pragma unroll
             for (int jj = 0; jj < PER; ++jj) sum += red[q][k][PER * hh + jj];
 #pragma unroll
             for (int sh = NV; sh < 64; sh <<= 1) sum += __shfl_xor(sum, sh);
-            // global index k + (NV/4)(q & 1) + (NV/2)(q >> 1) = o = 4 u + c: quads of
-            // lanes hold the 4 components of one l
+            // quads of lanes hold the 4 components of one l
             const int u = o >> 2, cc = o & 3;
             const int qb = lane & ~3;
             const double s0 = __shfl(sum, qb | 0), s1 = __shfl(sum, qb | 1), s2 = __shfl(sum, qb | 2),
