@@ -200,7 +200,7 @@ template <int R, bool SPIN> __device__ inline bool leg_live(const LegState<R, SP
 template <int R, bool SPIN, bool FULL, int NS>
 __device__ inline void advance_steps(LegState<R, SPIN> &S, const double4 *sT, int t0, int t1, int c, int lmax) {
     if (FULL) {
-#pragma unroll
+#pragma unroll 2
         for (int u = 0; u < NS; ++u) leg_advance<R, SPIN>(S, sT[t0 + u]);
     } else {
         for (int t = t0; t < t1; ++t)
@@ -424,9 +424,13 @@ __device__ inline void adj_fold(int u, double c0, double c1, double c2, double c
 template <int R, bool SPIN, int CH>
 __device__ inline void adj_block(LegState<R, SPIN> &S, const double4 *sT, int b, const double *fpr,
                                  const double *fpi, const double *fmr, const double *fmi, double *w) {
+    // coefficients one step ahead, not the whole block's at once (registers)
+    double3 tn = make_double3(sT[b].x, sT[b].y, sT[b].z);
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-        const double4 tc = sT[b + u];
+        const double3 tc = tn;
+        if (u + 1 < CH) tn = make_double3(sT[b + u + 1].x, sT[b + u + 1].y, sT[b + u + 1].z);
+        __builtin_amdgcn_sched_barrier(0);
         double cpl[R], cmi[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -795,11 +799,11 @@ static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out
 static int rings_knob(const char *name, int dflt) {
     const char *e = getenv(name);
     const int v = e ? atoi(e) : dflt;
-    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : dflt;
+    return (v >= 1 && v <= 4) || v == 8 ? v : dflt;
 }
 
 // Rings per lane: 2 for both directions unless PSHT_LEG_R (synthesis) or
-// PSHT_LEG_RA (adjoint), each 1, 2, 4 or 8, overrides it for tuning runs.
+// PSHT_LEG_RA (adjoint), each 1, 2, 3, 4 or 8, overrides it for tuning runs.
 int leg_rings_per_lane() {
     static const int r = rings_knob("PSHT_LEG_R", 2);
     return r;
@@ -862,6 +866,7 @@ hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, vo
                        reinterpret_cast<const double4 *>(p.leg->d_coef), static_cast<double4 *>(scratch), n, g.lmax, mscale);
     switch (p.leg_rings_per_item / 64) {
         case 1: leg_synth_r<1>(p, scratch, F, st); break;
+        case 3: leg_synth_r<3>(p, scratch, F, st); break;
         case 2: leg_synth_r<2>(p, scratch, F, st); break;
         case 8: leg_synth_r<8>(p, scratch, F, st); break;
         default: leg_synth_r<4>(p, scratch, F, st); break;
@@ -900,6 +905,7 @@ hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, 
     if (p.n_leg_items_adj == 0) return hipSuccess;
     switch (p.leg_rings_per_item_adj / 64) {
         case 1: leg_adjoint_r<1>(p, F, alm, mscale, st); break;
+        case 3: leg_adjoint_r<3>(p, F, alm, mscale, st); break;
         case 2: leg_adjoint_r<2>(p, F, alm, mscale, st); break;
         case 8: leg_adjoint_r<8>(p, F, alm, mscale, st); break;
         default: leg_adjoint_r<4>(p, F, alm, mscale, st); break;
