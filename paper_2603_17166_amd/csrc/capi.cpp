@@ -313,13 +313,15 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     return PSHT_OK;
 }
 
-// Smallest number of maps that takes the batched Legendre pass (PSHT_MM_MIN
-// overrides it for tuning runs; a value above 8 disables the batched pass).
+// Smallest number of maps that takes the batched Legendre pass: its cost does
+// not depend on the number of maps (the MFMA tiles always hold 8), and it
+// beats the one-map pass from about 4.6 maps on (PSHT_MM_MIN overrides it
+// for tuning runs; a value above 8 disables the batched pass).
 int leg_batch_min() {
     static int v = [] {
         const char *e = getenv("PSHT_MM_MIN");
-        const int x = e ? atoi(e) : 4;
-        return x >= 2 ? x : 4;
+        const int x = e ? atoi(e) : 5;
+        return x >= 2 ? x : 5;
     }();
     return v;
 }

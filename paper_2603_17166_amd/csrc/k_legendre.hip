@@ -647,13 +647,17 @@ struct LegBatchArgs {
     int nb;              // maps in this launch, 1..8
 };
 
-// (at most 168 VGPRs: three waves per SIMD measured faster than two)
+// Register budget of two waves per SIMD: the accumulators then stay in VGPRs
+// (a three-wave budget split them into AGPRs and copied them around every
+// block); the compiler needs 162 VGPRs, the LDS (14 KB) allows 11 waves per CU.
 template <bool SPIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_leg_synth_mm(LegBatchArgs bt) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_leg_synth_mm(LegBatchArgs bt) {
     const LegArgs &a = bt.a;
     __shared__ double4 sT[2][kStage];
-    __shared__ double sZ[2][kStage][2][16];  // [slot][l][sign][column]
-    __shared__ double sL[2][2][4][64];       // [buffer][sign][k][ring]
+    // one buffer of coefficient columns: the next chunk waits in registers
+    // (nz) until the current one is done, which keeps the LDS at 18 KB
+    __shared__ double sZ[kStage][2][16];  // [l][sign][column]
+    __shared__ double sL[2][4][64];          // [sign][k][ring]
     const int idx = leg_item_index(blockIdx.x, a.group);
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
@@ -676,16 +680,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             v = reinterpret_cast<const double4 *>(bt.Q0 + (int64_t)b * bt.stride)[base + l];
         return v;
     };
-    auto store_z = [&](int slot, int e, double4 v) {
+    auto store_z = [&](int e, double4 v) {
         const int lo = e >> 3, b = e & 7;
-        sZ[slot][lo][0][2 * b] = v.x;
-        sZ[slot][lo][0][2 * b + 1] = v.y;
-        sZ[slot][lo][1][2 * b] = v.z;
-        sZ[slot][lo][1][2 * b + 1] = v.w;
+        sZ[lo][0][2 * b] = v.x;
+        sZ[lo][0][2 * b + 1] = v.y;
+        sZ[lo][1][2 * b] = v.z;
+        sZ[lo][1][2 * b + 1] = v.w;
     };
     if (lane < 32) sT[0][lane] = stage_entry(T4, nullptr, l0, lmax, lane);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) store_z(0, lane + 64 * i, load_z(l0, lane + 64 * i));
+    for (int i = 0; i < 4; ++i) store_z(lane + 64 * i, load_z(l0, lane + 64 * i));
 
     LegState<1, SPIN> S;
     leg_init<1, SPIN>(a, it, lane, S);
@@ -696,7 +700,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int kk = lane >> 4, jj = lane & 15;
     __syncthreads();
 
-    int slot = 0, buf = 0;
+    int slot = 0;
     for (int c = l0; c <= lmax; c += kStage) {
         const bool has_next = c + kStage <= lmax;
         double4 nt, nz[4];
@@ -721,29 +725,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                     vm = (SPIN ? S.um[0] : S.up[0]) * cm;
                     if (c + t < lmax) leg_advance<1, SPIN>(S, sT[slot][t]);
                 }
-                sL[buf][0][k][lane] = vp;
-                sL[buf][1][k][lane] = vm;
+                sL[0][k][lane] = vp;
+                sL[1][k][lane] = vm;
             }
             if (scaled) {
                 leg_renorm<1, SPIN>(S);
                 scaled = leg_any_scaled<1, SPIN>(S);
             }
-            // One wave per workgroup: the barrier orders this block's LDS
-            // writes before its reads; the next block writes the other buffer.
+            // One wave per workgroup, whose LDS operations run in program order:
+            // the barrier only keeps the compiler from moving this block's
+            // writes past its reads (and the next block's writes past them).
             __syncthreads();
             // columns of l = c + b4 + kk (zero past lmax)
-            const double bp = sZ[slot][b4 + kk][0][jj], bm = sZ[slot][b4 + kk][1][jj];
+            const double bp = sZ[b4 + kk][0][jj], bm = sZ[b4 + kk][1][jj];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                Dp[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sL[buf][0][kk][16 * q + jj], bp, Dp[q], 0, 0, 0);
-                Dm[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sL[buf][1][kk][16 * q + jj], bm, Dm[q], 0, 0, 0);
+                Dp[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sL[0][kk][16 * q + jj], bp, Dp[q], 0, 0, 0);
+                Dm[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sL[1][kk][16 * q + jj], bm, Dm[q], 0, 0, 0);
             }
-            buf ^= 1;
+            __syncthreads();
         }
         if (has_next) {
             if (lane < 32) sT[slot ^ 1][lane] = nt;
+            __syncthreads();  // the last block's column reads come first
 #pragma unroll
-            for (int i = 0; i < 4; ++i) store_z(slot ^ 1, lane + 64 * i, nz[i]);
+            for (int i = 0; i < 4; ++i) store_z(lane + 64 * i, nz[i]);
         }
         __syncthreads();
         slot ^= 1;

@@ -1,4 +1,4 @@
-"""Multi-map calls.  Synthesis: the batched Legendre pass (groups of 4..8
+"""Multi-map calls.  Synthesis: the batched Legendre pass (groups of 5..8
 maps through FP64 MFMA); adjoint: one Legendre pass per map behind the
 shared call.  Every map of a call against the oracle (10 epsilon) and
 against the one-map call, including group splits (nmaps > 8), the polar
@@ -32,14 +32,15 @@ def rel(a, b):
 
 CASES = [
     # lmax, spin, cap radius (deg), npoints, eps, precision, nmaps
-    (96, 2, 12.0, 2000, 1e-10, "fp64", 4),
+    (96, 2, 12.0, 2000, 1e-10, "fp64", 5),
     (128, 0, 10.0, 3000, 1e-10, "fp64", 8),
     (80, 1, 20.0, 1500, 1e-10, "fp64", 5),
     (64, 3, 30.0, 1500, 1e-12, "fp64", 9),
     (200, 2, 6.0, 3000, 1e-10, "fp64", 11),
     (256, 2, 15.0, 3000, 1e-5, "fp32", 8),
     (40, 2, 150.0, 1500, 1e-10, "fp64", 6),   # full-sky fallback
-    (700, 2, 3.0, 2500, 1e-10, "fp64", 4),    # deep polar: rescaled seeds
+    (700, 2, 3.0, 2500, 1e-10, "fp64", 5),    # deep polar: rescaled seeds
+    (64, 2, 12.0, 1500, 1e-10, "fp64", 4),    # below the batching threshold: one pass per map
 ]
 
 
