@@ -177,8 +177,7 @@ psht_status psht_plan_geometry(int lmax, int spin, double theta_star, double eps
  *                               eq. syn on ring j; zero where m is cut off.
  *   PSHT_STAGE_LEGENDRE_ADJOINT : in = F' (same layout), out = alm [2][nalm];
  *                               the exact transpose of the stage above.
- * The Legendre synthesis stage allocates and frees its own scratch and
- * synchronises hip_stream before returning. */
+ * Both are asynchronous on hip_stream and allocate nothing. */
 enum { PSHT_STAGE_LEGENDRE_SYNTH = 1, PSHT_STAGE_LEGENDRE_ADJOINT = 2 };
 psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, void *hip_stream);
 

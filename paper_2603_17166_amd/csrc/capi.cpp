@@ -307,8 +307,7 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     p.ws_F = align256((size_t)(2 * g.mmax + 1) * g.nring * 16);
     p.ws_V = align256((size_t)g.rows_used * (2 * g.mmax + 1) * cs);
     p.ws_U = align256((size_t)g.rows_used * g.Nphi * cs);
-    p.ws_Q = align256(psht::leg_synth_scratch_bytes(g));
-    p.ws_per_map = p.ws_F + p.ws_V + p.ws_U + p.ws_Q;
+    p.ws_per_map = p.ws_F + p.ws_V + p.ws_U;
     *out = plan.release();
     return PSHT_OK;
 }
@@ -376,17 +375,16 @@ psht_status synth_impl(psht_plan plan, int nmaps, const void *alm, void *map, vo
         // groups of batch_min..8 maps share one batched (MFMA) Legendre pass
         const int nb = nmaps - i >= batch_min ? std::min(nmaps - i, psht::kMaxLegBatch) : 1;
         char *ws0 = static_cast<char *>(workspace) + (size_t)i * plan->ws_per_map;
-        const size_t offQ = plan->ws_F + plan->ws_V + plan->ws_U;
         const char *a0 = static_cast<const char *>(alm) + i * alm_bytes;
         hipError_t e;
         if (nb > 1)
             e = timed(P, PSHT_T_LEG_SYNTH, st, [&] {
-                return psht::launch_leg_synth_batch(P, nb, a0, (int64_t)alm_bytes, ws0, ws0 + offQ,
-                                                    (int64_t)plan->ws_per_map, mscale, st);
+                return psht::launch_leg_synth_batch(P, nb, a0, (int64_t)alm_bytes, ws0, (int64_t)plan->ws_per_map,
+                                                    mscale, st);
             });
         else
             e = timed(P, PSHT_T_LEG_SYNTH, st, [&] {
-                return psht::launch_leg_synth(P, a0, reinterpret_cast<double *>(ws0), ws0 + offQ, mscale, st);
+                return psht::launch_leg_synth(P, a0, reinterpret_cast<double *>(ws0), mscale, st);
             });
         for (int b = 0; b < nb && e == hipSuccess; ++b) {
             char *ws = ws0 + (size_t)b * plan->ws_per_map;
@@ -532,15 +530,8 @@ psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, voi
     const psht::Geometry &g = plan->g;
     hipError_t e;
     if (stage == PSHT_STAGE_LEGENDRE_SYNTH) {
-        void *scratch = nullptr;
-        e = hipMalloc(&scratch, std::max<size_t>(16, psht::leg_synth_scratch_bytes(g)));
-        if (e == hipSuccess) e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
-        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), scratch, 1.0, st);
-        if (scratch) {
-            hipError_t e2 = hipStreamSynchronize(st);
-            if (e == hipSuccess) e = e2;
-            (void)hipFree(scratch);
-        }
+        e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
+        if (e == hipSuccess) e = psht::launch_leg_synth(*plan, in, static_cast<double *>(out), 1.0, st);
     } else if (stage == PSHT_STAGE_LEGENDRE_ADJOINT) {
         e = psht::launch_fill_zero(out, (size_t)(g.lmax + 1) * (g.lmax + 2) / 2 * 2 * 16, st);
         if (e == hipSuccess) e = psht::launch_leg_adjoint(*plan, static_cast<const double *>(in), out, 1.0, st);

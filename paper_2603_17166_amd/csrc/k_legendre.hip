@@ -42,10 +42,10 @@ struct LegArgs {
     const int32_t *ring_mmax;
     int nring, lmax, spin, mmax;
     int64_t nalm;
-    const double4 *Q;  // synthesis: per (l, m) {Re, Im of P(g + i c), Re, Im of P(conj g + i conj c)}
+    const double2 *g, *c;  // synthesis input: g_lm and c_lm, complex [nalm] each
     double *alm_out;   // adjoint output, complex [2][nalm]
     double *F;         // complex [2 mmax + 1][nring]: synthesis output / adjoint input
-    double mscale;     // adjoint: extra factor on the outputs of order m >= 1
+    double mscale;     // extra factor on the inputs (synthesis) or outputs (adjoint) of order m >= 1
 };
 
 // Block -> item map: the `group` items of one order m run on the same XCD
@@ -64,24 +64,6 @@ __device__ inline void rescale_sel(double &cur, double &prev, int &k) {
     cur *= f;
     prev *= f;
     k += big ? 1 : 0;
-}
-
-// Per-call combination of the coefficients with the normalisation P_l:
-// Q = P {g_r - c_i, g_i + c_r, g_r + c_i, c_r - g_i} (imaginary parts of the
-// m = 0 coefficients dropped), for every (l, m <= mmax).
-__global__ void k_leg_prep(const double2 *g, const double2 *c, const double4 *coef, double4 *Q, int64_t n, int lmax,
-                           double mscale) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 a = g[i], b = c[i];
-    double P = coef[i].w;
-    if (i <= lmax) {  // m = 0
-        a.y = 0.0;
-        b.y = 0.0;
-    } else {
-        P *= mscale;
-    }
-    Q[i] = make_double4((a.x - b.y) * P, (a.y + b.x) * P, (a.x + b.y) * P, (b.x - a.y) * P);
 }
 
 template <int R, bool SPIN> struct LegState {
@@ -150,14 +132,39 @@ template <int R, bool SPIN> __device__ inline void leg_renorm(LegState<R, SPIN> 
 // while the current chunk is computed from wave-uniform (broadcast) LDS reads.
 constexpr int kStage = 32;
 
-// Entry `lane` of the chunk starting at c: lanes 0..31 read the recurrence
-// table, lanes 32..63 the second stream (when there is one).
-__device__ inline double4 stage_entry(const double4 *T4, const double4 *Q4, int c, int lmax, int lane) {
+// Entry `lane` of the chunk starting at c: the recurrence table, zero past lmax.
+__device__ inline double4 stage_entry(const double4 *T4, int c, int lmax, int lane) {
+    const int l = c + (lane & 31);
+    return l <= lmax ? T4[l] : make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
+// The synthesis multiplies lambda+ by P (g + i c) and lambda- by P (conj g +
+// i conj c) (Sec. I, with lambda_l = P_l mu_l): the four real combinations
+// P {g_r - c_i, g_i + c_r, g_r + c_i, c_r - g_i} of order m at degree l
+// (coefficient index k), with the imaginary parts of the m = 0 coefficients
+// dropped and the inputs of order m >= 1 scaled by mscale.
+__device__ inline double4 synth_combo(const double2 *g, const double2 *c, const double4 *coef, int64_t k, int m,
+                                      double mscale) {
+    double2 a = g[k], b = c[k];
+    double P = coef[k].w;
+    if (m == 0) {
+        a.y = 0.0;
+        b.y = 0.0;
+    } else {
+        P *= mscale;
+    }
+    return make_double4((a.x - b.y) * P, (a.y + b.x) * P, (a.x + b.y) * P, (b.x - a.y) * P);
+}
+
+// Synthesis staging: lanes 0..31 read the recurrence table, lanes 32..63 form
+// the coefficient combinations of the same 32 degrees.
+__device__ inline double4 stage_entry_synth(const LegArgs &a, const double4 *T4, int64_t base, int m, int c,
+                                            int lmax, int lane) {
     const int l = c + (lane & 31);
     double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
     if (l <= lmax) {
         if (lane < 32) v = T4[l];
-        else if (Q4) v = Q4[l];
+        else v = synth_combo(a.g, a.c, a.coef, base + l, m, a.mscale);
     }
     return v;
 }
@@ -274,8 +281,7 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
 
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double4 *T4 = a.coef + base;
-    const double4 *Q4 = a.Q + base;
-    sbuf[0][lane >> 5][lane & 31] = stage_entry(T4, Q4, l0, lmax, lane);
+    sbuf[0][lane >> 5][lane & 31] = stage_entry_synth(a, T4, base, m, l0, lmax, lane);
 
     LegState<R, SPIN> S;
     leg_init<R, SPIN>(a, it, lane, S);
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
     for (int c = l0; c <= lmax; c += kStage) {
         const bool has_next = c + kStage <= lmax;
         double4 nv;
-        if (has_next) nv = stage_entry(T4, Q4, c + kStage, lmax, lane);
+        if (has_next) nv = stage_entry_synth(a, T4, base, m, c + kStage, lmax, lane);
         const double4 *sT = sbuf[slot][0], *sQ = sbuf[slot][1];
         const int n = min(kStage, lmax + 1 - c);
         if (!scaled && has_next) {
@@ -524,7 +530,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
 
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double4 *T4 = a.coef + base;
-    if (lane < 32) sbuf[0][lane] = stage_entry(T4, nullptr, l0, lmax, lane);
+    if (lane < 32) sbuf[0][lane] = stage_entry(T4, l0, lmax, lane);
 
     LegState<R, SPIN> S;
     leg_init<R, SPIN>(a, it, lane, S);
@@ -541,7 +547,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     for (int c = l0; c <= lmax; c += kStage) {
         const bool has_next = c + kStage <= lmax;
         double4 nv;
-        if (has_next && lane < 32) nv = stage_entry(T4, nullptr, c + kStage, lmax, lane);
+        if (has_next && lane < 32) nv = stage_entry(T4, c + kStage, lmax, lane);
         const double4 *sT = sbuf[slot];
         const int n = min(kStage, lmax + 1 - c);
         for (int b = 0; b < n; b += kAdjChunk) {
@@ -641,9 +647,10 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 struct LegBatchArgs {
     LegArgs a;           // work list of 64-ring chunks, tables, rings
-    const char *Q0;      // Q of map 0 (double4 per (l, m <= mmax)); map b at Q0 + b * stride
+    const char *alm0;    // coefficients (g, c) of map 0, complex [2][nalm]; map b at alm0 + b * alm_stride
+    int64_t alm_stride;  // bytes
     char *F0;            // F of map 0; map b at F0 + b * stride
-    int64_t stride;      // bytes between consecutive maps' Q and F
+    int64_t stride;      // bytes between consecutive maps' F (their workspaces)
     int nb;              // maps in this launch, 1..8
 };
 
@@ -669,15 +676,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const double4 *T4 = a.coef + base;
 
     // Staging of a chunk of kStage steps from l = c: lanes 0..31 load the
-    // recurrence table, every lane 4 (l, map) entries of the columns
-    // (l = c + e / 8, map = e % 8), zero past lmax and past nb.  The loads of
+    // recurrence table, every lane forms 4 (l, map) entries of the columns
+    // (l = c + e / 8, map = e % 8) from the coefficients, zero past lmax and
+    // past nb.  The loads of
     // the next chunk are issued before the current chunk is computed and
     // written to the other LDS slot after it.
     auto load_z = [&](int c, int e) {
         const int lo = e >> 3, b = e & 7, l = c + lo;
         double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (b < bt.nb && l <= lmax)
-            v = reinterpret_cast<const double4 *>(bt.Q0 + (int64_t)b * bt.stride)[base + l];
+        if (b < bt.nb && l <= lmax) {
+            const double2 *gb = reinterpret_cast<const double2 *>(bt.alm0 + (int64_t)b * bt.alm_stride);
+            v = synth_combo(gb, gb + a.nalm, a.coef, base + l, m, a.mscale);
+        }
         return v;
     };
     auto store_z = [&](int e, double4 v) {
@@ -687,7 +697,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         sZ[lo][1][2 * b] = v.z;
         sZ[lo][1][2 * b + 1] = v.w;
     };
-    if (lane < 32) sT[0][lane] = stage_entry(T4, nullptr, l0, lmax, lane);
+    if (lane < 32) sT[0][lane] = stage_entry(T4, l0, lmax, lane);
 #pragma unroll
     for (int i = 0; i < 4; ++i) store_z(lane + 64 * i, load_z(l0, lane + 64 * i));
 
@@ -705,7 +715,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const bool has_next = c + kStage <= lmax;
         double4 nt, nz[4];
         if (has_next) {
-            if (lane < 32) nt = stage_entry(T4, nullptr, c + kStage, lmax, lane);
+            if (lane < 32) nt = stage_entry(T4, c + kStage, lmax, lane);
 #pragma unroll
             for (int i = 0; i < 4; ++i) nz[i] = load_z(c + kStage, lane + 64 * i);
         }
@@ -777,7 +787,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // Arguments over the synthesis work list (64 R rings per item); the adjoint
 // replaces items and nitems by its own list.
 template <int R>
-static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out, double *F) {
+static LegArgs leg_args(const psht_plan_s &p, const void *alm_in, const void *alm_out, double *F) {
     const Geometry &g = p.g;
     LegArgs a;
     a.items = p.d_leg_items;
@@ -795,7 +805,8 @@ static LegArgs leg_args(const psht_plan_s &p, const void *Q, const void *alm_out
     a.spin = g.spin;
     a.mmax = g.mmax;
     a.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
-    a.Q = static_cast<const double4 *>(Q);
+    a.g = static_cast<const double2 *>(alm_in);
+    a.c = a.g ? a.g + a.nalm : nullptr;
     a.alm_out = static_cast<double *>(const_cast<void *>(alm_out));
     a.F = F;
     a.mscale = 1.0;
@@ -820,17 +831,10 @@ int leg_adj_rings_per_lane() {
     return r;
 }
 
-// Number of (l, m) coefficient entries with m <= mmax.
-static int64_t leg_entries(const Geometry &g) {
-    const int64_t mm = g.mmax;
-    return (mm + 1) * (g.lmax + 1) - mm * (mm + 1) / 2;
-}
-
-size_t leg_synth_scratch_bytes(const Geometry &g) { return (size_t)leg_entries(g) * sizeof(double4); }
-
 template <int R>
-static void leg_synth_r(const psht_plan_s &p, const void *Q, double *F, hipStream_t st) {
-    LegArgs a = leg_args<R>(p, Q, nullptr, F);
+static void leg_synth_r(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st) {
+    LegArgs a = leg_args<R>(p, alm, nullptr, F);
+    a.mscale = mscale;
     dim3 grid(p.n_leg_items), block(64);
     if (p.g.spin) hipLaunchKernelGGL((k_leg_synth<R, true>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_leg_synth<R, false>), grid, block, 0, st, a);
@@ -861,48 +865,34 @@ static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, doub
     }
 }
 
-hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, double mscale,
-                            hipStream_t st) {
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st) {
     if (p.n_leg_items == 0) return hipSuccess;
-    const Geometry &g = p.g;
-    const int64_t n = leg_entries(g);
-    const int64_t nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
-    const double2 *gg = static_cast<const double2 *>(alm);
-    hipLaunchKernelGGL(k_leg_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gg, gg + nalm,
-                       reinterpret_cast<const double4 *>(p.leg->d_coef), static_cast<double4 *>(scratch), n, g.lmax, mscale);
     switch (p.leg_rings_per_item / 64) {
-        case 1: leg_synth_r<1>(p, scratch, F, st); break;
-        case 3: leg_synth_r<3>(p, scratch, F, st); break;
-        case 2: leg_synth_r<2>(p, scratch, F, st); break;
-        case 8: leg_synth_r<8>(p, scratch, F, st); break;
-        default: leg_synth_r<4>(p, scratch, F, st); break;
+        case 1: leg_synth_r<1>(p, alm, F, mscale, st); break;
+        case 3: leg_synth_r<3>(p, alm, F, mscale, st); break;
+        case 2: leg_synth_r<2>(p, alm, F, mscale, st); break;
+        case 8: leg_synth_r<8>(p, alm, F, mscale, st); break;
+        default: leg_synth_r<4>(p, alm, F, mscale, st); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_leg_synth_batch(const psht_plan_s &p, int nb, const void *alm0, int64_t alm_stride, char *F0,
-                                  char *Q0, int64_t ws_stride, double mscale, hipStream_t st) {
+                                  int64_t ws_stride, double mscale, hipStream_t st) {
     if (nb < 1 || nb > kMaxLegBatch) return hipErrorInvalidValue;
     if (p.n_leg_items64 == 0) return hipSuccess;
-    const Geometry &g = p.g;
-    const int64_t n = leg_entries(g);
-    const int64_t nalm = (int64_t)(g.lmax + 1) * (g.lmax + 2) / 2;
-    for (int b = 0; b < nb; ++b) {
-        const double2 *gg = reinterpret_cast<const double2 *>(static_cast<const char *>(alm0) + b * alm_stride);
-        hipLaunchKernelGGL(k_leg_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gg, gg + nalm,
-                           reinterpret_cast<const double4 *>(p.leg->d_coef),
-                           reinterpret_cast<double4 *>(Q0 + b * ws_stride), n, g.lmax, mscale);
-    }
     LegBatchArgs bt;
     bt.a = leg_args<1>(p, nullptr, nullptr, nullptr);
     bt.a.items = p.d_leg_items64;
     bt.a.nitems = p.n_leg_items64;
-    bt.a.group = (g.nring + 63) / 64;
-    bt.Q0 = Q0;
+    bt.a.group = (p.g.nring + 63) / 64;
+    bt.a.mscale = mscale;
+    bt.alm0 = static_cast<const char *>(alm0);
+    bt.alm_stride = alm_stride;
     bt.F0 = F0;
     bt.stride = ws_stride;
     bt.nb = nb;
-    if (g.spin) hipLaunchKernelGGL((k_leg_synth_mm<true>), dim3(p.n_leg_items64), dim3(64), 0, st, bt);
+    if (p.g.spin) hipLaunchKernelGGL((k_leg_synth_mm<true>), dim3(p.n_leg_items64), dim3(64), 0, st, bt);
     else hipLaunchKernelGGL((k_leg_synth_mm<false>), dim3(p.n_leg_items64), dim3(64), 0, st, bt);
     return hipGetLastError();
 }

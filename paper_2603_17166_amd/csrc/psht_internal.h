@@ -132,7 +132,7 @@ struct psht_plan_s {
     int32_t *d_tile_start = nullptr;  // ntiles + 1, in entries (2 per slot)
     int64_t n_entries = 0;            // slot entries of all tiles (points + dummies)
     // workspace layout (bytes, per map)
-    size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_Q = 0, ws_per_map = 0;
+    size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_per_map = 0;
     size_t resident = 0;
     std::vector<void *> allocations;
     // per-stage HIP-event timing (PSHT_T_* indices)
@@ -146,19 +146,16 @@ struct psht_plan_s {
 namespace psht {
 
 // Stage launchers (defined in the .hip files).  All asynchronous on `st`.
-// Synthesis needs leg_synth_scratch_bytes(g) of scratch (per-call coefficient combinations).
 // `mscale` multiplies the coefficients (synthesis) or the outputs (adjoint) of
 // every order m >= 1; 1 for the plain transforms.
-hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, void *scratch, double mscale,
-                            hipStream_t st);
-size_t leg_synth_scratch_bytes(const Geometry &g);
+hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st);
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st);
 // Legendre synthesis of nb <= kMaxLegBatch maps in one pass (MFMA): map b reads
-// its coefficients at alm0 + b alm_stride and uses the F and Q buffers at
-// F0 + b ws_stride and Q0 + b ws_stride (its own workspace).
+// its coefficients at alm0 + b alm_stride and writes F at F0 + b ws_stride
+// (its own workspace).
 constexpr int kMaxLegBatch = 8;
 hipError_t launch_leg_synth_batch(const psht_plan_s &p, int nb, const void *alm0, int64_t alm_stride, char *F0,
-                                  char *Q0, int64_t ws_stride, double mscale, hipStream_t st);
+                                  int64_t ws_stride, double mscale, hipStream_t st);
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st);
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st);
 hipError_t launch_phi_synth(const psht_plan_s &p, const void *V, void *U, hipStream_t st);
