@@ -514,10 +514,23 @@ __device__ inline void adj_renorm(LegState<R, SPIN> &S, const double2 *Fp, const
     }
 }
 
-// CH: values of l per transposed reduction (4 or 8).
+// x from lane i ^ 1 and i ^ 2 of the quad (DPP quad permutations, 64-bit values).
+__device__ inline double quad_xor1(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double quad_xor2(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x4E, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x4E, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// CH = 8 values of l per transposed reduction.
 template <int R, bool SPIN, int CH>
 __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
-    constexpr int kAdjChunk = CH, NV = 4 * CH;  // NV partial sums per block of CH steps
+    static_assert(CH == 8, "the output stage maps 8 steps x 2 components x 4 lanes onto the wave");
+    constexpr int kAdjChunk = CH;
     __shared__ double4 sbuf[2][kStage];
     __shared__ double red[4][CH][17];
     const int idx = leg_item_index(blockIdx.x, a.group);
@@ -588,39 +601,45 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                 adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
                 scaled = leg_any_scaled<R, SPIN>(S);
             }
-            // The remaining sum over the 16 lanes of each row q = lane >> 4 goes
-            // through LDS.  Output o = 4 u + c (step u, component c) sits in row
-            // q = 2 (c >> 1) + (u & 1), value k = 2 (u >> 1) + (c & 1); 64/NV lanes
-            // share an output and each sums 16 NV/64 columns.
+            // The remaining sums over the 16 lanes of each row go through LDS.
+            // Step u, component c sits in row 2 (c >> 1) + (u & 1), value
+            // 2 (u >> 1) + (c & 1): A_x (c = x) and B_x (c = 2 + x) share the
+            // value index, two rows apart.  Lane (u = lane >> 3, x = bit 2,
+            // h = lane & 3) adds columns 4h .. 4h + 3 of both, the quad of lanes
+            // h = 0..3 completes the sums, and lanes h = 0 and 1 form the g~ and
+            // c~ outputs of component x.
 #pragma unroll
             for (int k = 0; k < kAdjChunk; ++k) red[row][k][col] = w[k];
             __syncthreads();
-            constexpr int PARTS = 64 / NV, PER = 16 / PARTS;
-            const int o = lane & (NV - 1), hh = lane / NV;
-            const int q = 2 * ((o & 3) >> 1) + ((o >> 2) & 1), k = 2 * (o >> 3) + (o & 1);
-            double sum = 0.0;
+            const int u = lane >> 3, x = (lane >> 2) & 1, h = lane & 3;
+            const int qa = u & 1, kv = 2 * (u >> 1) + x;
+            double sa = 0.0, sb = 0.0;
 #pragma unroll
-            for (int jj = 0; jj < PER; ++jj) sum += red[q][k][PER * hh + jj];
-#pragma unroll
-            for (int sh = NV; sh < 64; sh <<= 1) sum += __shfl_xor(sum, sh);
-            // quads of lanes hold the 4 components of one l
-            const int u = o >> 2, cc = o & 3;
-            const int qb = lane & ~3;
-            const double s0 = __shfl(sum, qb | 0), s1 = __shfl(sum, qb | 1), s2 = __shfl(sum, qb | 2),
-                         s3 = __shfl(sum, qb | 3);
-            const int t = b + u, l = c + t;
-            if (hh == 0 && t < n) {
-                const double P = sT[t].w;
-                const int64_t kk = base + l;
+            for (int j = 0; j < 4; ++j) {
+                sa += red[qa][kv][4 * h + j];
+                sb += red[qa + 2][kv][4 * h + j];
+            }
+            sa += quad_xor1(sa);
+            sb += quad_xor1(sb);
+            sa += quad_xor2(sa);
+            sb += quad_xor2(sb);
+            const int t = b + u;
+            // Im g~_l0 and Im c~_l0 vanish exactly for m = 0 (reality condition).
+            const bool imag = h == 0 ? x == 1 : x == 0;
+            if (h < 2 && t < n && !(m == 0 && imag)) {
+                const int64_t kk = base + c + t;
+                const double hP = (m == 0 ? 0.5 : 0.5 * a.mscale) * sT[t].w;
                 double val;
                 double *dst;
-                const double hP = (m == 0 ? 0.5 : 0.5 * a.mscale) * P;
-                if (cc == 0) { val = -hP * (s0 + sgn_s * s2); dst = a.alm_out + 2 * kk; }
-                else if (cc == 1) { val = -hP * (s1 + sgn_s * s3); dst = a.alm_out + 2 * kk + 1; }
-                else if (cc == 2) { val = -hP * (s1 - sgn_s * s3); dst = a.alm_out + 2 * (a.nalm + kk); }
-                else { val = hP * (s0 - sgn_s * s2); dst = a.alm_out + 2 * (a.nalm + kk) + 1; }
-                // Im g~_l0 and Im c~_l0 vanish exactly (reality condition).
-                if (!(m == 0 && (cc & 1))) atomicAdd(dst, val);
+                if (h == 0) {  // g~: -hP (A + (-1)^s B), component x
+                    val = -hP * (sa + sgn_s * sb);
+                    dst = a.alm_out + 2 * kk + x;
+                } else {  // c~ = (i/2) P (A - (-1)^s B): Im from the real parts, Re from the imaginary ones
+                    const double d = hP * (sa - sgn_s * sb);
+                    val = x == 0 ? d : -d;
+                    dst = a.alm_out + 2 * (a.nalm + kk) + (1 - x);
+                }
+                atomicAdd(dst, val);
             }
             __syncthreads();
         }
@@ -840,15 +859,6 @@ static void leg_synth_r(const psht_plan_s &p, const void *alm, double *F, double
     else hipLaunchKernelGGL((k_leg_synth<R, false>), grid, block, 0, st, a);
 }
 
-// l per transposed reduction of the adjoint: 8 unless PSHT_ADJ_CH=4 for tuning runs.
-static int leg_adj_chunk() {
-    static int c = [] {
-        const char *e = getenv("PSHT_ADJ_CH");
-        return (e && atoi(e) == 4) ? 4 : 8;
-    }();
-    return c;
-}
-
 template <int R>
 static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
     LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
@@ -856,13 +866,8 @@ static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, doub
     a.nitems = p.n_leg_items_adj;
     a.mscale = mscale;
     dim3 grid(p.n_leg_items_adj), block(64);
-    if (leg_adj_chunk() == 4) {
-        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 4>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 4>), grid, block, 0, st, a);
-    } else {
-        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8>), grid, block, 0, st, a);
-    }
+    if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8>), grid, block, 0, st, a);
 }
 
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st) {
