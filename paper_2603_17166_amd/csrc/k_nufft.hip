@@ -91,24 +91,50 @@ typedef const double *UniformPtr;
 __host__ __device__ inline UniformPtr uniform_ptr(const double *p) { return p; }
 #endif
 
-template <int W>
-__device__ inline void es_weights(double X, int a0, double beta, UniformPtr C, double *k) {
+// NS weight sets at once (the coordinates X[s] with origins a0[s] into k[s][]):
+// each table coefficient is read once and used by the NS Horner chains, so only
+// a few coefficients are live in SGPRs at a time (evaluating the sets one after
+// another let the compiler hoist every coefficient and spill SGPRs into VGPR
+// lanes, one v_readlane per use).
+template <int W, int NS>
+__device__ inline void es_weights_n(const double *X, const int *a0, double beta, UniformPtr C, double (*k)[W]) {
     constexpr int P = W + 1 > 12 ? W + 1 : 12, NC = (W - 1) / 2;
     constexpr int PE = (P % 2 == 0) ? P : P - 1, PO = (P % 2 == 1) ? P : P - 1;
-    const double v = 2.0 * (X - (double)a0) - (double)(W - 1), v2 = v * v;
-    k[0] = es_kernel((v + (double)(W - 1)) * (1.0 / W), beta);
-    k[W - 1] = es_kernel((v - (double)(W - 1)) * (1.0 / W), beta);
+    double v[NS], v2[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        v[s] = 2.0 * (X[s] - (double)a0[s]) - (double)(W - 1);
+        v2[s] = v[s] * v[s];
+        k[s][0] = es_kernel((v[s] + (double)(W - 1)) * (1.0 / W), beta);
+        k[s][W - 1] = es_kernel((v[s] - (double)(W - 1)) * (1.0 / W), beta);
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double e = C[PE * NC + c];
+        double e[NS], o[NS];
+        const double ce = C[PE * NC + c], co = C[PO * NC + c];
 #pragma unroll
-        for (int q = PE - 2; q >= 0; q -= 2) e = fma(e, v2, C[q * NC + c]);
-        double o = C[PO * NC + c];
+        for (int s = 0; s < NS; ++s) {
+            e[s] = ce;
+            o[s] = co;
+        }
 #pragma unroll
-        for (int q = PO - 2; q >= 1; q -= 2) o = fma(o, v2, C[q * NC + c]);
-        o *= v;
-        k[c + 1] = e + o;
-        if (W - 2 - c != c + 1) k[W - 2 - c] = e - o;
+        for (int q = PE - 2; q >= 0; q -= 2) {
+            const double cq = C[q * NC + c];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) e[s] = fma(e[s], v2[s], cq);
+        }
+#pragma unroll
+        for (int q = PO - 2; q >= 1; q -= 2) {
+            const double cq = C[q * NC + c];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) o[s] = fma(o[s], v2[s], cq);
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double os = o[s] * v[s];
+            k[s][c + 1] = e[s] + os;
+            if (W - 2 - c != c + 1) k[s][W - 2 - c] = e[s] - os;
+        }
     }
 }
 
@@ -153,9 +179,13 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         // By construction of the sort 0 <= li < tile_x and 0 <= lj < tile_y; the
         // guard only keeps LDS accesses in bounds.
         if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
-        double kx[W], ky[W];
-        es_weights<W>(X, a0, a.beta, sC, kx);
-        es_weights<W>(Y, b0, a.beta, sC, ky);
+        double kw[2][W];
+        {
+            const double xs[2] = {X, Y};
+            const int os[2] = {a0, b0};
+            es_weights_n<W, 2>(xs, os, a.beta, sC, kw);
+        }
+        const double *kx = kw[0], *ky = kw[1];
         double accr = 0.0, acci = 0.0;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -177,9 +207,8 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
     }
 }
 
-// (at most 128 VGPRs: four waves per SIMD measured faster than three)
 template <typename T, int W>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spread(NufftArgs a, const typename CplxT<T>::type *map,
+__global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const typename CplxT<T>::type *map,
                                                          T *U) {
     typedef typename CplxT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -207,13 +236,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (b0m < 0) b0m += a.Nphi;
         const int li = a0 - a.row_lo - r0, lj = b0m - c0;
         if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
-        double kx[W], ky[W], kx2[W], ky2[W];
-        es_weights<W>(X, a0, a.beta, sC, kx);
-        es_weights<W>(Y, b0, a.beta, sC, ky);
-        // the partner has the same cell, but its own unwrapped origin: across
-        // phi = 0 its b0 differs from this point's by Nphi
-        es_weights<W>(X2, stencil_origin(X2, W), a.beta, sC, kx2);
-        es_weights<W>(Y2, stencil_origin(Y2, W), a.beta, sC, ky2);
+        double kw[4][W];
+        {
+            // the partner has the same cell, but its own unwrapped origin: across
+            // phi = 0 its b0 differs from this point's by Nphi
+            const double xs[4] = {X, Y, X2, Y2};
+            const int os[4] = {a0, b0, stencil_origin(X2, W), stencil_origin(Y2, W)};
+            es_weights_n<W, 4>(xs, os, a.beta, sC, kw);
+        }
+        const double *kx = kw[0], *ky = kw[1], *kx2 = kw[2], *ky2 = kw[3];
         const C f = map[a.perm[p]];
         const int pm2 = a.perm[p + 1];
         C f2;
