@@ -268,13 +268,10 @@ __device__ inline void synth_clear_scaled(const LegState<R, SPIN> &S, double *fp
     }
 }
 
+// One work item of the synthesis with R rings per lane (the item holds at
+// most 64 R rings).
 template <int R, bool SPIN>
-__global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
-    __shared__ double4 sbuf[2][2][kStage + 1];  // one spare entry: the pipelined loop reads one step ahead
-    const int idx = leg_item_index(blockIdx.x, a.group);
-    if (idx >= a.nitems) return;
-    const LegItem it = a.items[idx];
-    if (it.je <= it.jb) return;
+__device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, double4 (*sbuf)[2][kStage + 1]) {
     const int m = it.m, s = a.spin, lane = threadIdx.x;
     const int l0 = m > s ? m : s, lmax = a.lmax;
     if (l0 > lmax) return;
@@ -377,6 +374,19 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
         Fp[j] = make_double2(-fpr[r], -fpi[r]);
         if (m != 0) Fm[j] = make_double2(sgn_neg * fmr[r], sgn_neg * fmi[r]);
     }
+}
+
+// An item with at most 64 rings (the remainder of an order's ring range)
+// runs the one-ring-per-lane body, at half the work of the R = 2 body.
+template <int R, bool SPIN>
+__global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
+    __shared__ double4 sbuf[2][2][kStage + 1];  // one spare entry: the pipelined loop reads one step ahead
+    const int idx = leg_item_index(blockIdx.x, a.group);
+    if (idx >= a.nitems) return;
+    const LegItem it = a.items[idx];
+    if (it.je <= it.jb) return;
+    if (R > 1 && it.je - it.jb <= 64) leg_synth_item<1, SPIN>(a, it, sbuf);
+    else leg_synth_item<R, SPIN>(a, it, sbuf);
 }
 
 // ---------------------------------------------------------------- adjoint
