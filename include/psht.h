@@ -189,18 +189,21 @@ psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, voi
 psht_status psht_fft(int n, int batch, int sign, int fp32, const void *in, void *out, void *hip_stream);
 
 /* ---- Per-stage timing ------------------------------------------------------
- * With timing enabled, every psht_synth / psht_adjoint call on the plan records
- * a pair of HIP events around each stage launch on the call's stream;
- * psht_plan_timing synchronises those events and returns, per stage, the
- * summed elapsed milliseconds and the number of launches since timing was
- * (re-)enabled.  Stage indices: PSHT_T_* below.  Not thread-safe: one caller
- * at a time per plan while timing is on. */
+ * psht_plan_set_timing(plan, stages): stages = 0 turns timing off; otherwise it
+ * is a bitmask of the stages to time (bit PSHT_T_x; PSHT_T_ALL for every
+ * stage).  Every later psht_synth / psht_adjoint call on the plan then records
+ * a pair of HIP events around each selected stage launch on the call's stream.
+ * The call resets the totals and creates the events ahead (for 32 calls), so
+ * that timing one stage adds two event records per call and nothing else.
+ * psht_plan_timing synchronises the events and returns, per stage, the summed
+ * elapsed milliseconds and the number of launches since timing was (re-)set.
+ * Not thread-safe: one caller at a time per plan while timing is on. */
 enum {
     PSHT_T_LEG_SYNTH = 0, PSHT_T_THETA_SYNTH = 1, PSHT_T_PHI_SYNTH = 2, PSHT_T_INTERP = 3,
     PSHT_T_GRID_ZERO = 4, PSHT_T_SPREAD = 5, PSHT_T_PHI_ADJ = 6, PSHT_T_THETA_ADJ = 7,
-    PSHT_T_ALM_ZERO = 8, PSHT_T_LEG_ADJ = 9, PSHT_T_COUNT = 10
+    PSHT_T_ALM_ZERO = 8, PSHT_T_LEG_ADJ = 9, PSHT_T_COUNT = 10, PSHT_T_ALL = (1 << 10) - 1
 };
-psht_status psht_plan_set_timing(psht_plan plan, int enable);
+psht_status psht_plan_set_timing(psht_plan plan, int stages);
 psht_status psht_plan_timing(psht_plan plan, double *ms, int64_t *launches);
 
 /* Host evaluation (diagnostics and tests) of

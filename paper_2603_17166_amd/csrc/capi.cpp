@@ -74,7 +74,7 @@ hipEvent_t take_event(psht_plan_s &p) {
 
 // Runs one stage launch, bracketed by timing events when timing is on.
 template <typename Fn> hipError_t timed(psht_plan_s &p, int stage, hipStream_t st, Fn fn) {
-    if (!p.timing) return fn();
+    if (!((p.timing >> stage) & 1u)) return fn();
     hipEvent_t a = take_event(p), b = take_event(p);
     if (!a || !b) return fn();
     (void)hipEventRecord(a, st);
@@ -458,7 +458,7 @@ psht_status psht_synth_grad(psht_plan plan, int nmaps, const void *alm_grad, voi
 
 void psht_plan_destroy(psht_plan plan) { free_plan(plan); }
 
-psht_status psht_plan_set_timing(psht_plan plan, int enable) {
+psht_status psht_plan_set_timing(psht_plan plan, int stages) {
     if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
     for (auto &e : plan->pending) {
         (void)hipEventSynchronize(e.second.second);
@@ -470,7 +470,14 @@ psht_status psht_plan_set_timing(psht_plan plan, int enable) {
         plan->t_ms[i] = 0;
         plan->t_launches[i] = 0;
     }
-    plan->timing = enable != 0;
+    plan->timing = (unsigned)stages & (unsigned)PSHT_T_ALL;
+    // events for 32 calls ahead: none is created while timed work is issued
+    const int want = 64 * __builtin_popcount(plan->timing);
+    while ((int)plan->event_pool.size() < want) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return fail(PSHT_ERR_DEVICE, "creating timing events");
+        plan->event_pool.push_back(e);
+    }
     return PSHT_OK;
 }
 

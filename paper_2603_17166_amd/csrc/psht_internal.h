@@ -136,7 +136,7 @@ struct psht_plan_s {
     size_t resident = 0;
     std::vector<void *> allocations;
     // per-stage HIP-event timing (PSHT_T_* indices)
-    bool timing = false;
+    unsigned timing = 0;  // bitmask of the stages to time
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> event_pool;
     double t_ms[PSHT_T_COUNT] = {0};

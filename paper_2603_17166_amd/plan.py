@@ -155,9 +155,14 @@ class Plan:
                                                 ws.numel(), _stream(stream)))
         return out[0] if single else out
 
-    def set_timing(self, enable: bool = True) -> None:
-        """Record HIP events around every stage launch of later calls (and reset the totals)."""
-        _lib.check(_lib.load().psht_plan_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable: bool = True, stages=None) -> None:
+        """Record HIP events around the stage launches of later calls (every stage,
+        or only those named in `stages`) and reset the totals."""
+        mask = 0
+        if enable:
+            mask = (1 << len(_lib.STAGE_NAMES)) - 1 if stages is None else \
+                sum(1 << _lib.STAGE_NAMES.index(s) for s in stages)
+        _lib.check(_lib.load().psht_plan_set_timing(self._h, mask))
 
     def timing(self) -> dict:
         """{stage: (total ms, launches)} since timing was enabled (synchronises the events)."""
