@@ -37,16 +37,20 @@ template <typename C> __device__ inline C cmul(C a, C b) {
 }
 template <typename C, typename S> __device__ inline C cscale(C a, S s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
 
+// A transform's factorization as kernel arguments: the radix of pass p in bits
+// 4p .. 4p + 3 of `code` (radices up to 13, at most 16 passes for n <= 8192),
+// so it occupies two scalar registers instead of an array.
 struct FftDev {
     int n, npass;
-    int radix[24];
+    unsigned long long code;
 };
 
 static FftDev to_dev(const FftFactors &f) {
     FftDev d;
     d.n = f.n;
     d.npass = f.npass;
-    for (int i = 0; i < 24; ++i) d.radix[i] = i < f.npass ? f.radix[i] : 1;
+    d.code = 0;
+    for (int i = 0; i < f.npass && i < 16; ++i) d.code |= (unsigned long long)(f.radix[i] & 15) << (4 * i);
     return d;
 }
 
@@ -190,7 +194,7 @@ template <typename T, int MAXN>
 __device__ void lds_fft(typename CT<T>::type *buf, const FftDev &f, int sign, const double2 *tw) {
     int Ns = 1;
     for (int p = 0; p < f.npass; ++p) {
-        const int R = f.radix[p];
+        const int R = (int)((f.code >> (4 * p)) & 15);
         switch (R) {
             case 4: fft_pass<T, 4, MAXN>(buf, f.n, Ns, sign, tw); break;
             case 2: fft_pass<T, 2, MAXN>(buf, f.n, Ns, sign, tw); break;

@@ -32,7 +32,7 @@ bool fft_factor(int n, FftFactors &f) {
     int r = n;
     for (int q : order) {
         while (r % q == 0) {
-            if (f.npass >= 24) return false;
+            if (f.npass >= 16) return false;  // the device code holds at most 16 passes (4 bits each)
             f.radix[f.npass++] = q;
             r /= q;
         }

@@ -64,7 +64,7 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
 // Factorization of an FFT length into radices 4, 2, 3, 5, 7, 11, 13.
 struct FftFactors {
     int n = 0, npass = 0;
-    int radix[24];
+    int radix[16];
 };
 bool fft_factor(int n, FftFactors &f);
 bool is_smooth(int n, const int *primes, int np);
