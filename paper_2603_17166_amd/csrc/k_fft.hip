@@ -139,10 +139,13 @@ template <typename C, int R> __device__ inline void dft(C *v, int sign) {
     }
 }
 
-// Threads of a workgroup transforming up to MAXN points.  The longest tier
-// holds up to 128 KB of LDS, one workgroup per CU: 1024 threads give each
-// SIMD four waves to hide the LDS and twiddle latency.
-__host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2048 ? 256 : (maxn <= 4096 ? 512 : 1024); }
+// Threads of a workgroup transforming up to MAXN points.  The passes are
+// bound by latency (LDS round trips and barriers), so what counts is the
+// number of transforms in flight per CU: up to 2560 points (40 KB of FP64
+// data) four workgroups of 256 threads fit a CU, where two of 512 did.  The
+// longest tier holds up to 128 KB of LDS, one workgroup per CU: 1024 threads
+// give each SIMD four waves.
+__host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2560 ? 256 : (maxn <= 4096 ? 512 : 1024); }
 
 // One Stockham pass of radix R on buf[0..n) with stride Ns.  Every thread
 // holds NB butterflies in registers; NB follows from the largest transform
@@ -445,6 +448,7 @@ template <typename F> static hipError_t set_lds(F kern, size_t bytes) {
 template <typename Fn> static void tier_dispatch(int n, Fn fn) {
     if (n <= 1024) fn(std::integral_constant<int, 1024>());
     else if (n <= 2048) fn(std::integral_constant<int, 2048>());
+    else if (n <= 2560) fn(std::integral_constant<int, 2560>());
     else if (n <= 4096) fn(std::integral_constant<int, 4096>());
     else fn(std::integral_constant<int, 8192>());
 }
