@@ -182,7 +182,9 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     const int fmax = fp32 ? psht::kFftMaxLds32 : psht::kFftMaxLds64;
     if (g.Ntheta > fmax || g.N2 > fmax)
         return fail(PSHT_ERR_UNSUPPORTED, "Theta grid of " + std::to_string(g.Ntheta) + " exceeds the LDS FFT limit");
-    p.phi_split = g.Nphi > fmax;
+    // Rows longer than the 2560-point tier run as two half-length transforms in
+    // workgroups of their own (twice the transforms in flight per CU); Nphi is even.
+    p.phi_split = g.Nphi > fmax || (g.Nphi > 2560 && g.Nphi % 2 == 0);
     if (p.phi_split && g.Nphi / 2 > fmax)
         return fail(PSHT_ERR_UNSUPPORTED, "phi grid of " + std::to_string(g.Nphi) + " exceeds the LDS FFT limit");
 
@@ -228,23 +230,44 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
                 }
             }
         };
+        // Synthesis order.  The kernel deals item slot (x + 8 q) group + i to the
+        // XCD x, in the order of q and i; the items of each XCD are placed in
+        // those slots longest first by their cost in the synthesis, where an
+        // item of at most 64 rings runs the one-ring-per-lane body at 1/R of
+        // the cost (longest-processing-time-first list scheduling; in the plain
+        // order these short remainders sat between the full items of their m).
+        auto order_for_synth = [&](std::vector<psht::LegItem> &items, int chunk, int R) {
+            const int group = (g.nring + chunk - 1) / chunk;
+            const int nq = (int)(items.size() / group) / 8;
+            auto cost = [&](const psht::LegItem &it) {
+                if (it.je <= it.jb) return 0.0;
+                const double steps = lmax + 1 - std::max(it.m, spin);
+                return (R > 1 && it.je - it.jb <= 64) ? steps / R : steps;
+            };
+            for (int x = 0; x < 8; ++x) {
+                std::vector<size_t> slots;
+                for (int q = 0; q < nq; ++q)
+                    for (int i = 0; i < group; ++i) slots.push_back((size_t)(x + 8 * q) * group + i);
+                std::vector<psht::LegItem> mine;
+                for (size_t sl : slots) mine.push_back(items[sl]);
+                std::stable_sort(mine.begin(), mine.end(),
+                                 [&](const psht::LegItem &u, const psht::LegItem &v) { return cost(u) > cost(v); });
+                for (size_t k = 0; k < slots.size(); ++k) items[slots[k]] = mine[k];
+            }
+        };
         std::vector<psht::LegItem> items;
         const int chunk = 64 * psht::leg_rings_per_lane();
         build_items(chunk, items);
+        order_for_synth(items, chunk, psht::leg_rings_per_lane());
         p.n_leg_items = (int)items.size();
         p.leg_rings_per_item = chunk;
         if (!upload(p, p.d_leg_items, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
+        // the adjoint runs one body for every item: the plain order (m ascending) is longest first
         const int chunk_adj = 64 * psht::leg_adj_rings_per_lane();
         p.leg_rings_per_item_adj = chunk_adj;
-        if (chunk_adj == chunk) {
-            p.d_leg_items_adj = p.d_leg_items;
-            p.n_leg_items_adj = p.n_leg_items;
-        } else {
-            build_items(chunk_adj, items);
-            p.n_leg_items_adj = (int)items.size();
-            if (!upload(p, p.d_leg_items_adj, items, st))
-                return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
-        }
+        build_items(chunk_adj, items);
+        p.n_leg_items_adj = (int)items.size();
+        if (!upload(p, p.d_leg_items_adj, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
         build_items(64, items);
         p.n_leg_items64 = (int)items.size();
         if (!upload(p, p.d_leg_items64, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");

@@ -346,6 +346,32 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_adjoint(StageArgs a
 }
 
 // -------------------------------------------------------------- phi stage
+//
+// Long rows are split into two half-length transforms, each in a workgroup of
+// its own, so that twice as many transforms are in flight per CU (a 5880-point
+// FP64 row takes 94 KB of LDS, a whole CU's worth for one workgroup).  Both
+// directions split their output index, so the halves never write the same
+// element:
+//   synthesis, outputs k = 2 k' + h:  U[2 k' + h] = sum_m V_m e^{2 pi i m h / Np} e^{2 pi i m k' / nh},
+//     a half-length transform of the spectrum with m taken mod nh;
+//   adjoint, frequencies m = 2 m' + h:  V_m = sum_{k < nh} y_h[k] e^{-2 pi i m' k / nh},
+//     y_h[k] = (U[k] + (-1)^h U[k + nh]) e^{-2 pi i h k / Np}.
+
+// Row and half of block b.  With split rows the two halves of a row go to
+// blocks 16 q + x and 16 q + 8 + x, which the round-robin dealing of blocks
+// places on the same XCD, so their interleaved outputs meet in one L2.
+__device__ inline void phi_block(int b, bool split, int &r, int &h) {
+    if (!split) {
+        r = b;
+        h = 0;
+        return;
+    }
+    const int x = b & 7, q = b >> 3;
+    h = q & 1;
+    r = 8 * (q >> 1) + x;
+}
+
+static inline unsigned phi_grid(int rows, bool split) { return split ? 16u * (unsigned)((rows + 7) / 8) : (unsigned)rows; }
 
 template <typename T, int MAXN>
 __global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_synth(StageArgs a, const typename CT<T>::type *V,
@@ -353,29 +379,29 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_synth(StageArgs a, co
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
-    const int64_t r = blockIdx.x;
+    int r, h;
+    phi_block(blockIdx.x, a.split, r, h);
+    if (r >= a.rows_used) return;
     const int Np = a.Nphi, nh = a.split ? Np / 2 : Np, mm = a.mmax;
-    const C *Vr = V + r * (2 * mm + 1);
-    C *Ur = U + r * Np;
+    const C *Vr = V + (int64_t)r * (2 * mm + 1);
+    C *Ur = U + (int64_t)r * Np;
     C z;
     z.x = z.y = (T)0;
-    for (int h = 0; h < (a.split ? 2 : 1); ++h) {
-        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = z;
-        __syncthreads();
-        for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads(MAXN)) {
-            const int m = mi - mm;
-            C v = cscale(Vr[mi], (T)(1.0 / a.psihat_p[abs(m)]));
-            if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, +1));
-            buf[m < 0 ? m + nh : m] = v;
-        }
-        __syncthreads();
-        lds_fft<T, MAXN>(buf, a.fnp, +1, a.tw_np);
-        if (a.split) {
-            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[2 * k + h] = buf[k];
-        } else {
-            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[k] = buf[k];
-        }
-        __syncthreads();
+    for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = z;
+    __syncthreads();
+    // |m| <= mmax < nh / 2: the m taken mod nh land on distinct entries
+    for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads(MAXN)) {
+        const int m = mi - mm;
+        C v = cscale(Vr[mi], (T)(1.0 / a.psihat_p[abs(m)]));
+        if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, +1));
+        buf[m < 0 ? m + nh : m] = v;
+    }
+    __syncthreads();
+    lds_fft<T, MAXN>(buf, a.fnp, +1, a.tw_np);
+    if (a.split) {
+        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[2 * k + h] = buf[k];
+    } else {
+        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[k] = buf[k];
     }
 }
 
@@ -385,27 +411,29 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_adjoint(StageArgs a, 
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
-    const int64_t r = blockIdx.x;
+    int r, h;
+    phi_block(blockIdx.x, a.split, r, h);
+    if (r >= a.rows_used) return;
     const int Np = a.Nphi, nh = a.split ? Np / 2 : Np, mm = a.mmax;
-    C *Vr = V + r * (2 * mm + 1);
-    const C *Ur = U + r * Np;
-    for (int h = 0; h < (a.split ? 2 : 1); ++h) {
-        if (a.split) {
-            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = Ur[2 * k + h];
-        } else {
-            for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = Ur[k];
+    C *Vr = V + (int64_t)r * (2 * mm + 1);
+    const C *Ur = U + (int64_t)r * Np;
+    if (a.split) {
+        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) {
+            const C u0 = Ur[k], u1 = Ur[k + nh];
+            buf[k] = h ? cmul(csub(u0, u1), twiddle<C>(a.tw_np_full, k, -1)) : cadd(u0, u1);
         }
-        __syncthreads();
-        lds_fft<T, MAXN>(buf, a.fnp, -1, a.tw_np);
-        for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads(MAXN)) {
-            const int m = mi - mm;
-            C v = buf[m < 0 ? m + nh : m];
-            if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, -1));
-            v = cscale(v, (T)(1.0 / a.psihat_p[abs(m)]));
-            if (h) v = cadd(v, Vr[mi]);
-            Vr[mi] = v;
-        }
-        __syncthreads();
+    } else {
+        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = Ur[k];
+    }
+    __syncthreads();
+    lds_fft<T, MAXN>(buf, a.fnp, -1, a.tw_np);
+    // frequencies of this half: m = mi - mmax with m = h (mod 2) when split
+    const int step = a.split ? 2 : 1, mi0 = a.split ? ((h + mm) & 1) : 0;
+    for (int mi = mi0 + step * (int)threadIdx.x; mi <= 2 * mm; mi += step * fft_threads(MAXN)) {
+        const int m = mi - mm;
+        const int f = m < 0 ? m + Np : m;
+        const C v = buf[a.split ? (f >> 1) : f];
+        Vr[mi] = cscale(v, (T)(1.0 / a.psihat_p[abs(m)]));
     }
 }
 
@@ -485,7 +513,8 @@ static void phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V,
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_phi_synth<T, MX>, lds);
-        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(p.g.rows_used), dim3(fft_threads(MX)), lds, st, a,
+        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads(MX)), lds,
+                           st, a,
                            static_cast<const C *>(V), static_cast<C *>(U));
     });
 }
@@ -498,7 +527,8 @@ static void phi_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_phi_adjoint<T, MX>, lds);
-        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(p.g.rows_used), dim3(fft_threads(MX)), lds, st, a,
+        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads(MX)),
+                           lds, st, a,
                            static_cast<const C *>(U), static_cast<C *>(V));
     });
 }

@@ -114,7 +114,7 @@ struct psht_plan_s {
     psht::LegItem *d_leg_items = nullptr;
     int n_leg_items = 0;
     int leg_rings_per_item = 0;
-    psht::LegItem *d_leg_items_adj = nullptr;  // adjoint list (its own rings per lane; may alias d_leg_items)
+    psht::LegItem *d_leg_items_adj = nullptr;  // adjoint list (its own rings per lane and order)
     int n_leg_items_adj = 0;
     int leg_rings_per_item_adj = 0;
     psht::LegItem *d_leg_items64 = nullptr;  // 64-ring chunks (batched-maps kernel)
