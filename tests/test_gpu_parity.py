@@ -43,7 +43,10 @@ def alm_rel(a, b, lmax):
 
 # ------------------------------------------------------------------ FFT (P13)
 
-@pytest.mark.parametrize("n", [1, 2, 3, 13, 91, 105, 143, 1155, 2310, 2352, 4050, 6000, 8192, 7 * 11 * 13 * 4])
+# the lengths cover every radix pass, the tiers of the LDS kernel up to 8192
+# points and the phi-row lengths of the lmax 2048 workload (5880 and its half)
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 10, 12, 13, 14, 15, 91, 105, 143, 210, 1155, 2310, 2352, 2940, 4050, 5880,
+                               6000, 8192, 7 * 11 * 13 * 4])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_fft_vs_numpy(n, fp32):
     say("fft n=%d fp32=%s" % (n, fp32))
