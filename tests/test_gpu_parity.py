@@ -272,3 +272,22 @@ def test_workspace_too_small():
     code = _lib.load().psht_synth(plan._h, 1, a.data_ptr(), out.data_ptr(), ws.data_ptr(), 16,
                                    torch.cuda.current_stream().cuda_stream)
     assert code == _lib.PSHT_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("lmax, radius_deg", [(64, 20), (1024, 50)])
+def test_adjoint_overwrites_output(lmax, radius_deg):
+    """The adjoint writes every coefficient whatever its output buffer held (it
+    accumulates into the output with atomics after clearing it), for a small
+    plan and for one with 2 mmax + 1 >= 1024 Theta-stage columns."""
+    say("adjoint into a junk-filled output: lmax %d, cap %d deg" % (lmax, radius_deg))
+    th, ph = syn.uniform_cap(20000, radius_deg * DEG, 9100 + lmax)
+    plan = Plan(th, ph, lmax, 2, 1e-10)
+    assert (2 * plan.info["mmax"] + 1 >= 1024) == (lmax == 1024)
+    f = dev(syn.gaussian_map(20000, 9200 + lmax))
+    ref = plan.adjoint(f, out=torch.zeros((1, 2, syn.nalm(lmax)), dtype=torch.complex128, device="cuda"))
+    junk = torch.full_like(ref, complex(float("nan"), 1e300))
+    got = plan.adjoint(f, out=junk)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(torch.view_as_real(got)).all())
+    d = (got - ref).abs().max().item() / ref.abs().max().item()
+    assert d < 1e-12, d
