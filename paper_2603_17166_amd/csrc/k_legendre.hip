@@ -414,23 +414,26 @@ __device__ inline void swap16(double &x, double &y) {
 // into the transposed reduction, as soon as they are computed: a 32-lane swap
 // keeps component c + 2 bit5(i) in lane i, summed over lanes i and i ^ 32; the
 // two steps u and u + 1 then share a 16-lane swap that keeps step
-// u + bit4(i), summed over {i, i ^ 16, i ^ 32, i ^ 48}.  After CH steps w
-// holds CH values per lane: w[2 (u / 2) + (c & 1)].
+// u + bit4(i), summed over {i, i ^ 16, i ^ 32, i ^ 48}; the value of step
+// pair u / 2 and component parity c & 1 goes to red[row][2 (u / 2) + (c & 1)][col].
 template <int CH>
-__device__ inline void adj_fold(int u, double c0, double c1, double c2, double c3, double *w) {
+__device__ inline void adj_fold(int u, double c0, double c1, double c2, double c3, double *w, double (*red)[CH][17],
+                                int row, int col) {
     swap32(c0, c2);
     c0 += c2;
     swap32(c1, c3);
     c1 += c3;
     const int p = u >> 1;
     if ((u & 1) == 0) {
-        w[2 * p] = c0;
-        w[2 * p + 1] = c1;
+        w[0] = c0;
+        w[1] = c1;
     } else {
-        swap16(w[2 * p], c0);
-        w[2 * p] += c0;
-        swap16(w[2 * p + 1], c1);
-        w[2 * p + 1] += c1;
+        // the pair's two values are final: to LDS at once, so that only two
+        // values per lane are live across the block
+        swap16(w[0], c0);
+        swap16(w[1], c1);
+        red[row][2 * p][col] = w[0] + c0;
+        red[row][2 * p + 1][col] = w[1] + c1;
     }
 }
 
@@ -439,7 +442,8 @@ __device__ inline void adj_fold(int u, double c0, double c1, double c2, double c
 // partial sums), the dependent recurrence updates last.
 template <int R, bool SPIN, int CH>
 __device__ inline void adj_block(LegState<R, SPIN> &S, const double4 *sT, int b, const double *fpr,
-                                 const double *fpi, const double *fmr, const double *fmi, double *w) {
+                                 const double *fpi, const double *fmr, const double *fmi, double *w,
+                                 double (*red)[CH][17], int row, int col) {
     // coefficients one step ahead, not the whole block's at once (registers)
     double3 tn = make_double3(sT[b].x, sT[b].y, sT[b].z);
 #pragma unroll
@@ -473,7 +477,7 @@ __device__ inline void adj_block(LegState<R, SPIN> &S, const double4 *sT, int b,
                 S.um[r] = nm;
             }
         }
-        adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w);
+        adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w, red, row, col);
     }
 }
 
@@ -576,7 +580,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
         for (int b = 0; b < n; b += kAdjChunk) {
             // per-lane partial sums over the lane's rings, 4 components per l,
             // folded step by step (adj_fold)
-            double w[kAdjChunk];
+            double w[2];
             const bool full = c + b + kAdjChunk <= lmax;  // every step of the block exists and advances
             if (scaled && !leg_live<R, SPIN>(S)) {
                 // every active lane below the double range: all partial sums
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                 continue;
             }
             if (full) {
-                adj_block<R, SPIN, CH>(S, sT, b, fpr, fpi, fmr, fmi, w);
+                adj_block<R, SPIN, CH>(S, sT, b, fpr, fpi, fmr, fmi, w, red, row, col);
             } else
 #pragma unroll
             for (int u = 0; u < kAdjChunk; ++u) {
@@ -605,7 +609,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                     }
                     if (c + t < lmax) leg_advance<R, SPIN>(S, sT[t]);
                 }
-                adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w);
+                adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w, red, row, col);
             }
             if (scaled) {
                 adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
@@ -618,8 +622,6 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
             // h = lane & 3) adds columns 4h .. 4h + 3 of both, the quad of lanes
             // h = 0..3 completes the sums, and lanes h = 0 and 1 form the g~ and
             // c~ outputs of component x.
-#pragma unroll
-            for (int k = 0; k < kAdjChunk; ++k) red[row][k][col] = w[k];
             __syncthreads();
             const int u = lane >> 3, x = (lane >> 2) & 1, h = lane & 3;
             const int qa = u & 1, kv = 2 * (u >> 1) + x;
