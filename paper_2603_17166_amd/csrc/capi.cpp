@@ -262,8 +262,24 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         p.n_leg_items = (int)items.size();
         p.leg_rings_per_item = chunk;
         if (!upload(p, p.d_leg_items, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
-        // the adjoint runs one body for every item: the plain order (m ascending) is longest first
-        const int chunk_adj = 64 * psht::leg_adj_rings_per_lane();
+        // The adjoint runs one body for every item: the plain order (m ascending) is
+        // longest first.  Three rings per lane take about 30 % fewer wave-steps than
+        // two but hold 168 registers (three waves per SIMD instead of four); they pay
+        // off when the items fill the GPU at least twice over (lmax 4096: adjoint
+        // 3.2 -> 2.6 ms in the FP32 form, 3.3 -> 3.1 ms in FP64), while with about
+        // one round of items (lmax 2048) the longest items set the time and three
+        // rings per lane were 28 % slower.
+        int ra = psht::leg_adj_rings_per_lane();
+        if (ra == 0) {
+            int dev = 0, ncu = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+            build_items(64 * 3, items);
+            size_t n3 = 0;
+            for (const auto &it : items) n3 += it.je > it.jb;
+            ra = (ncu > 0 && n3 >= (size_t)2 * ncu * 4 * 3) ? 3 : 2;
+        }
+        const int chunk_adj = 64 * ra;
         p.leg_rings_per_item_adj = chunk_adj;
         build_items(chunk_adj, items);
         p.n_leg_items_adj = (int)items.size();

@@ -850,15 +850,16 @@ static int rings_knob(const char *name, int dflt) {
     return (v >= 1 && v <= 4) || v == 8 ? v : dflt;
 }
 
-// Rings per lane: 2 for both directions unless PSHT_LEG_R (synthesis) or
-// PSHT_LEG_RA (adjoint), each 1, 2, 3, 4 or 8, overrides it for tuning runs.
+// Rings per lane: 2 for the synthesis unless PSHT_LEG_R (1, 2, 3, 4 or 8)
+// overrides it for tuning runs; for the adjoint PSHT_LEG_RA likewise, and
+// without it 0: the plan chooses 2 or 3 by the size of its work list.
 int leg_rings_per_lane() {
     static const int r = rings_knob("PSHT_LEG_R", 2);
     return r;
 }
 
 int leg_adj_rings_per_lane() {
-    static const int r = rings_knob("PSHT_LEG_RA", 2);
+    static const int r = rings_knob("PSHT_LEG_RA", 0);
     return r;
 }
 
