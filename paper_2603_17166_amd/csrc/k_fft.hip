@@ -145,7 +145,14 @@ template <typename C, int R> __device__ inline void dft(C *v, int sign) {
 // data) four workgroups of 256 threads fit a CU, where two of 512 did.  The
 // longest tier holds up to 128 KB of LDS, one workgroup per CU: 1024 threads
 // give each SIMD four waves.
-__host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2560 ? 256 : (maxn <= 4096 ? 512 : 1024); }
+template <typename T> __host__ __device__ constexpr int fft_threads(int maxn) {
+    if constexpr (sizeof(T) == 8) return maxn <= 2560 ? 256 : (maxn <= 4096 ? 512 : 1024);
+    // FP32 data takes half the LDS per transform: the longest tier (64 KB) fits
+    // two workgroups of 512 threads per CU (FP32 phi halves at lmax 4096:
+    // 0.15 -> 0.13 ms each way); 256 threads up to 4096 points made the Theta
+    // stage slower.
+    return maxn <= 2560 ? 256 : 512;
+}
 
 // One Stockham pass of radix R on buf[0..n) with stride Ns.  Every thread
 // holds NB butterflies in registers; NB follows from the largest transform
@@ -154,7 +161,7 @@ __host__ __device__ constexpr int fft_threads(int maxn) { return maxn <= 2560 ? 
 template <typename T, int R, int MAXN>
 __device__ void fft_pass(typename CT<T>::type *buf, int n, int Ns, int sign, const double2 *tw) {
     typedef typename CT<T>::type C;
-    constexpr int NT = fft_threads(MAXN);
+    constexpr int NT = fft_threads<T>(MAXN);
     constexpr int NB = (MAXN / R + NT - 1) / NT;
     const int nb = n / R;
     const int tws = n / (Ns * R);
@@ -215,17 +222,17 @@ __device__ void lds_fft(typename CT<T>::type *buf, const FftDev &f, int sign, co
 // ------------------------------------------------------------ plain rows
 
 template <typename T, int MAXN>
-__global__ __launch_bounds__(fft_threads(MAXN)) void k_fft_rows(FftDev f, int sign, const double2 *tw,
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_fft_rows(FftDev f, int sign, const double2 *tw,
                                                           const typename CT<T>::type *in,
                                                           typename CT<T>::type *out) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
     const int64_t row = blockIdx.x;
-    for (int k = threadIdx.x; k < f.n; k += fft_threads(MAXN)) buf[k] = in[row * f.n + k];
+    for (int k = threadIdx.x; k < f.n; k += fft_threads<T>(MAXN)) buf[k] = in[row * f.n + k];
     __syncthreads();
     lds_fft<T, MAXN>(buf, f, sign, tw);
-    for (int k = threadIdx.x; k < f.n; k += fft_threads(MAXN)) out[row * f.n + k] = buf[k];
+    for (int k = threadIdx.x; k < f.n; k += fft_threads<T>(MAXN)) out[row * f.n + k] = buf[k];
 }
 
 // ------------------------------------------------------------ Theta stage
@@ -254,7 +261,7 @@ __device__ inline int xcd_column(int b, int ncol) {
 static inline unsigned xcd_grid(int ncol) { return 8u * (unsigned)((ncol + 7) / 8); }
 
 template <typename T, int MAXN>
-__global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_synth(StageArgs a, const double2 *F,
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_synth(StageArgs a, const double2 *F,
                                                              typename CT<T>::type *V) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_synth(StageArgs a, 
     const double sig = ((a.spin + am) & 1) ? -1.0 : 1.0;  // mirror sign (-1)^(s+m)
     const int L = a.L, N2 = a.N2, NT = a.NT;
     const double2 *Fm = F + (int64_t)mi * a.nring;
-    for (int k = threadIdx.x; k < N2; k += fft_threads(MAXN)) {
+    for (int k = threadIdx.x; k < N2; k += fft_threads<T>(MAXN)) {
         const int j = k <= L ? k : N2 - k;
         const double wj = (k <= L ? 1.0 : sig) * a.ring_w[j];
         double2 v = make_double2(0.0, 0.0);
@@ -278,10 +285,10 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_synth(StageArgs a, 
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fn2, -1, a.tw_n2);  // N2 * Fourier coefficient
     // divide by N2 psihat(|n|) and pad to NT: n < 0 moves from N2 - |n| to NT - |n|
-    for (int n = 1 + threadIdx.x; n <= L; n += fft_threads(MAXN))
+    for (int n = 1 + threadIdx.x; n <= L; n += fft_threads<T>(MAXN))
         buf[NT - n] = cscale(buf[N2 - n], (T)(1.0 / (N2 * a.psihat_t[n])));
     __syncthreads();
-    for (int k = threadIdx.x; k < NT - L; k += fft_threads(MAXN)) {
+    for (int k = threadIdx.x; k < NT - L; k += fft_threads<T>(MAXN)) {
         if (k <= L) {
             buf[k] = cscale(buf[k], (T)(1.0 / (N2 * a.psihat_t[k])));
         } else {
@@ -293,7 +300,7 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_synth(StageArgs a, 
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnt, +1, a.tw_nt);
     const int64_t ldv = 2 * a.mmax + 1;
-    for (int r = threadIdx.x; r < a.rows_used; r += fft_threads(MAXN)) {
+    for (int r = threadIdx.x; r < a.rows_used; r += fft_threads<T>(MAXN)) {
         int row = (a.row_lo + r) % NT;
         if (row < 0) row += NT;
         V[(int64_t)r * ldv + mi] = buf[row];
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_synth(StageArgs a, 
 }
 
 template <typename T, int MAXN>
-__global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_adjoint(StageArgs a, const typename CT<T>::type *V,
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_adjoint(StageArgs a, const typename CT<T>::type *V,
                                                                double2 *F) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -314,9 +321,9 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_adjoint(StageArgs a
     const int64_t ldv = 2 * a.mmax + 1;
     C z;
     z.x = z.y = (T)0;
-    for (int k = threadIdx.x; k < NT; k += fft_threads(MAXN)) buf[k] = z;
+    for (int k = threadIdx.x; k < NT; k += fft_threads<T>(MAXN)) buf[k] = z;
     __syncthreads();
-    for (int r = threadIdx.x; r < a.rows_used; r += fft_threads(MAXN)) {
+    for (int r = threadIdx.x; r < a.rows_used; r += fft_threads<T>(MAXN)) {
         int row = (a.row_lo + r) % NT;
         if (row < 0) row += NT;
         buf[row] = V[(int64_t)r * ldv + mi];
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_adjoint(StageArgs a
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnt, -1, a.tw_nt);
     // keep |n| <= L, divide by N2 psihat, move n < 0 from NT - |n| to N2 - |n|
-    for (int k = threadIdx.x; k <= L; k += fft_threads(MAXN)) {
+    for (int k = threadIdx.x; k <= L; k += fft_threads<T>(MAXN)) {
         const T sc = (T)(1.0 / (N2 * a.psihat_t[k]));
         buf[k] = cscale(buf[k], sc);
         if (k >= 1) buf[N2 - k] = cscale(buf[NT - k], sc);
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_theta_adjoint(StageArgs a
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fn2, +1, a.tw_n2);
     double2 *Fm = F + (int64_t)mi * a.nring;
-    for (int j = threadIdx.x; j <= L; j += fft_threads(MAXN)) {
+    for (int j = threadIdx.x; j <= L; j += fft_threads<T>(MAXN)) {
         C v = buf[j];
         double re = v.x, im = v.y;
         if (j > 0) {
@@ -374,7 +381,7 @@ __device__ inline void phi_block(int b, bool split, int &r, int &h) {
 static inline unsigned phi_grid(int rows, bool split) { return split ? 16u * (unsigned)((rows + 7) / 8) : (unsigned)rows; }
 
 template <typename T, int MAXN>
-__global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_synth(StageArgs a, const typename CT<T>::type *V,
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_phi_synth(StageArgs a, const typename CT<T>::type *V,
                                                            typename CT<T>::type *U) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -387,10 +394,10 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_synth(StageArgs a, co
     C *Ur = U + (int64_t)r * Np;
     C z;
     z.x = z.y = (T)0;
-    for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = z;
+    for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) buf[k] = z;
     __syncthreads();
     // |m| <= mmax < nh / 2: the m taken mod nh land on distinct entries
-    for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads(MAXN)) {
+    for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads<T>(MAXN)) {
         const int m = mi - mm;
         C v = cscale(Vr[mi], (T)(1.0 / a.psihat_p[abs(m)]));
         if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, +1));
@@ -399,14 +406,14 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_synth(StageArgs a, co
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnp, +1, a.tw_np);
     if (a.split) {
-        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[2 * k + h] = buf[k];
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) Ur[2 * k + h] = buf[k];
     } else {
-        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) Ur[k] = buf[k];
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) Ur[k] = buf[k];
     }
 }
 
 template <typename T, int MAXN>
-__global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_adjoint(StageArgs a, const typename CT<T>::type *U,
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_phi_adjoint(StageArgs a, const typename CT<T>::type *U,
                                                              typename CT<T>::type *V) {
     typedef typename CT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -418,18 +425,18 @@ __global__ __launch_bounds__(fft_threads(MAXN)) void k_phi_adjoint(StageArgs a, 
     C *Vr = V + (int64_t)r * (2 * mm + 1);
     const C *Ur = U + (int64_t)r * Np;
     if (a.split) {
-        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) {
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) {
             const C u0 = Ur[k], u1 = Ur[k + nh];
             buf[k] = h ? cmul(csub(u0, u1), twiddle<C>(a.tw_np_full, k, -1)) : cadd(u0, u1);
         }
     } else {
-        for (int k = threadIdx.x; k < nh; k += fft_threads(MAXN)) buf[k] = Ur[k];
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) buf[k] = Ur[k];
     }
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnp, -1, a.tw_np);
     // frequencies of this half: m = mi - mmax with m = h (mod 2) when split
     const int step = a.split ? 2 : 1, mi0 = a.split ? ((h + mm) & 1) : 0;
-    for (int mi = mi0 + step * (int)threadIdx.x; mi <= 2 * mm; mi += step * fft_threads(MAXN)) {
+    for (int mi = mi0 + step * (int)threadIdx.x; mi <= 2 * mm; mi += step * fft_threads<T>(MAXN)) {
         const int m = mi - mm;
         const int f = m < 0 ? m + Np : m;
         const C v = buf[a.split ? (f >> 1) : f];
@@ -488,7 +495,7 @@ static void theta_synth_t(const psht_plan_s &p, const StageArgs &a, const double
     tier_dispatch(p.g.Ntheta, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_theta_synth<T, MX>, lds);
-        hipLaunchKernelGGL((k_theta_synth<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads(MX)), lds, st,
+        hipLaunchKernelGGL((k_theta_synth<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)), lds, st,
                            a, F, static_cast<C *>(V));
     });
 }
@@ -500,7 +507,7 @@ static void theta_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void
     tier_dispatch(p.g.Ntheta, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_theta_adjoint<T, MX>, lds);
-        hipLaunchKernelGGL((k_theta_adjoint<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads(MX)), lds,
+        hipLaunchKernelGGL((k_theta_adjoint<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)), lds,
                            st, a, static_cast<const C *>(V), F);
     });
 }
@@ -513,7 +520,7 @@ static void phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V,
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_phi_synth<T, MX>, lds);
-        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads(MX)), lds,
+        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads<T>(MX)), lds,
                            st, a,
                            static_cast<const C *>(V), static_cast<C *>(U));
     });
@@ -527,7 +534,7 @@ static void phi_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_phi_adjoint<T, MX>, lds);
-        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads(MX)),
+        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads<T>(MX)),
                            lds, st, a,
                            static_cast<const C *>(U), static_cast<C *>(V));
     });
@@ -572,7 +579,7 @@ static void fft_rows_t(const FftTable &t, int batch, int sign, const void *in, v
     tier_dispatch(t.n, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_fft_rows<T, MX>, lds);
-        hipLaunchKernelGGL((k_fft_rows<T, MX>), dim3(batch), dim3(fft_threads(MX)), lds, st, f, sign, tw,
+        hipLaunchKernelGGL((k_fft_rows<T, MX>), dim3(batch), dim3(fft_threads<T>(MX)), lds, st, f, sign, tw,
                            static_cast<const C *>(in), static_cast<C *>(out));
     });
 }
