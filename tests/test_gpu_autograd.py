@@ -144,7 +144,7 @@ def test_fp32_plan_gradient_vs_oracle():
 
 def test_autograd_patch_lmax3000_full_size():
     """Map-fitting loss on the 999 deg^2, lmax 3000, spin-2 patch (~3.6M points):
-    d = synth(second alm set) + 1% complex white noise; 12 coordinates by
+    d = synth(second alm set) + 1% complex white noise; 20 coordinates by
     central differences."""
     w = syn.autograd_patch()
     say("autograd patch: %d points" % w.npoints)
@@ -154,7 +154,7 @@ def test_autograd_patch_lmax3000_full_size():
     rms = float(d0.abs().pow(2).mean().sqrt())
     d = d0 + torch.as_tensor(syn.complex_noise(w.npoints, 0.01 * rms, syn.SEED_MAP + 50 + w.seed_base), device="cuda")
     a0 = torch.as_tensor(w.alm(0), device="cuda")
-    coords = _coords(w.lmax, w.spin, min(plan.info["mmax"], 400), 12, 95)
+    coords = _coords(w.lmax, w.spin, min(plan.info["mmax"], 400), 20, 95)
     err, g = _fd_check(plan, a0, d, coords, 2.0)
     say("autograd patch: finite-difference vs autograd, max rel %.2e" % err)
     assert err <= 1e-7
