@@ -79,6 +79,7 @@ CASES = [
     (128, 2, 10.0, 4000, 1e-5, "fp32"),
     (256, 0, 20.0, 3000, 1e-5, "fp32"),
     (40, 2, 150.0, 2000, 1e-10, "fp64"),    # patch too large: full-sky fallback
+    (1024, 2, 50.0, 3000, 1e-10, "fp64"),   # phi rows of more than 2560 points: two half-length transforms
 ]
 
 
