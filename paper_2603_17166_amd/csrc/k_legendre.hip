@@ -850,11 +850,11 @@ static int rings_knob(const char *name, int dflt) {
     return (v >= 1 && v <= 4) || v == 8 ? v : dflt;
 }
 
-// Rings per lane: 2 for the synthesis unless PSHT_LEG_R (1, 2, 3, 4 or 8)
-// overrides it for tuning runs; for the adjoint PSHT_LEG_RA likewise, and
-// without it 0: the plan chooses 2 or 3 by the size of its work list.
+// Rings per lane: PSHT_LEG_R (synthesis) and PSHT_LEG_RA (adjoint), each 1,
+// 2, 3, 4 or 8, fix them for tuning runs; without them 0, and the plan
+// chooses by the size of its work list (synthesis 1 or 2, adjoint 2 or 3).
 int leg_rings_per_lane() {
-    static const int r = rings_knob("PSHT_LEG_R", 2);
+    static const int r = rings_knob("PSHT_LEG_R", 0);
     return r;
 }
 

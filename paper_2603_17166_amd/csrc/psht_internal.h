@@ -181,8 +181,7 @@ hipError_t launch_point_sort_order(psht_plan_s &p, int32_t *d_keys, const int32_
                                    const double *tpy, const int32_t *tperm, hipStream_t st);
 
 // Rings per lane of the Legendre synthesis and adjoint kernels (a work item
-// covers 64 x this many rings); 0 from leg_adj_rings_per_lane() leaves the
-// adjoint's choice to the plan.
+// covers 64 x this many rings); 0 leaves the choice to the plan.
 int leg_rings_per_lane();
 int leg_adj_rings_per_lane();
 
