@@ -296,6 +296,42 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         const int chunk_adj = 64 * ra;
         p.leg_rings_per_item_adj = chunk_adj;
         build_items(chunk_adj, items);
+        // Small plans leave most of the GPU idle in the adjoint (a few hundred
+        // items for thousands of wave slots), and its time is that of the
+        // longest items.  There each (m, ring chunk) is cut into S l-segments,
+        // consecutive in the list: segment k outputs l in [l0 + a_k, l0 + a_{k+1})
+        // and runs the recurrence alone below l0 + a_k, about 0.3 of a full step.
+        // With that price the offsets a_k = C (1 - 0.7^k) / 0.3 give every
+        // segment the same cost C.
+        p.leg_adj_lsegs = 1;
+        if (ra == 2 && psht::leg_adj_rings_per_lane() == 0 && ncu > 0) {
+            const double rounds = (double)nonempty(items) / ((double)ncu * 4 * 4);
+            const int nseg = rounds > 0 ? std::min(8, (int)(0.6 / rounds)) : 1;
+            if (nseg > 1) {
+                std::vector<psht::LegItem> seg(items.size() * nseg, psht::LegItem{0, 0, 0, 0});
+                for (size_t q = 0; q < items.size(); ++q) {
+                    const psht::LegItem &it = items[q];
+                    const int l0 = std::max(it.m, spin), L = lmax + 1 - l0;
+                    if (it.je <= it.jb || L < 8 * nseg) {  // short: one segment, the others empty
+                        seg[q * nseg] = it;
+                        for (int k = 1; k < nseg; ++k) seg[q * nseg + k] = psht::LegItem{it.m, 0, 0, 0};
+                        continue;
+                    }
+                    const double C = 0.3 * L / (1.0 - std::pow(0.7, nseg));
+                    int lo = l0;
+                    for (int k = 0; k < nseg; ++k) {
+                        const int hi = k + 1 == nseg ? lmax + 1
+                                                     : l0 + (int)std::lround(C * (1.0 - std::pow(0.7, k + 1)) / 0.3);
+                        psht::LegItem s2 = it;
+                        s2.lseg = lo | ((k + 1 == nseg ? 0 : hi) << 16);
+                        seg[q * nseg + k] = s2;
+                        lo = hi;
+                    }
+                }
+                items.swap(seg);
+                p.leg_adj_lsegs = nseg;
+            }
+        }
         p.n_leg_items_adj = (int)items.size();
         if (!upload(p, p.d_leg_items_adj, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
         build_items(64, items);

@@ -541,7 +541,7 @@ __device__ inline double quad_xor2(double x) {
 }
 
 // CH = 8 values of l per transposed reduction.
-template <int R, bool SPIN, int CH>
+template <int R, bool SPIN, int CH, bool SEG>
 __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     static_assert(CH == 8, "the output stage maps 8 steps x 2 components x 4 lanes onto the wave");
     constexpr int kAdjChunk = CH;
@@ -554,6 +554,11 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     const int m = it.m, s = a.spin, lane = threadIdx.x;
     const int l0 = m > s ? m : s, lmax = a.lmax;
     if (l0 > lmax) return;
+    // l-segment of the item (small plans): outputs for l in [lacc, lhi]; the
+    // steps below lacc only run the recurrence
+    // (a kernel of its own, SEG, so that the plain one keeps its registers)
+    const int lacc = SEG ? it.lseg & 0xFFFF : 0;
+    const int lhi = SEG && (it.lseg >> 16) > 0 ? (it.lseg >> 16) - 1 : lmax;
 
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double4 *T4 = a.coef + base;
@@ -571,24 +576,27 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
     __syncthreads();
 
     int slot = 0;
-    for (int c = l0; c <= lmax; c += kStage) {
-        const bool has_next = c + kStage <= lmax;
+    for (int c = l0; c <= lhi; c += kStage) {
+        const bool has_next = c + kStage <= lhi;
         double4 nv;
         if (has_next && lane < 32) nv = stage_entry(T4, c + kStage, lmax, lane);
         const double4 *sT = sbuf[slot];
-        const int n = min(kStage, lmax + 1 - c);
+        const int n = min(kStage, lhi + 1 - c);
         for (int b = 0; b < n; b += kAdjChunk) {
             // per-lane partial sums over the lane's rings, 4 components per l,
             // folded step by step (adj_fold)
             double w[2];
-            const bool full = c + b + kAdjChunk <= lmax;  // every step of the block exists and advances
-            if (scaled && !leg_live<R, SPIN>(S)) {
-                // every active lane below the double range: all partial sums
-                // vanish, so the block needs neither sums nor reduction
-                if (full) advance_steps<R, SPIN, true, kAdjChunk>(S, sT, b, n, c, lmax);
-                else advance_steps<R, SPIN, false, kAdjChunk>(S, sT, b, min(b + kAdjChunk, n), c, lmax);
-                adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
-                scaled = leg_any_scaled<R, SPIN>(S);
+            const bool full = c + b + kAdjChunk <= lhi;  // every step of the block exists and advances
+            if ((SEG && c + b + kAdjChunk <= lacc) || (scaled && !leg_live<R, SPIN>(S))) {
+                // below the item's l-segment, or every active lane below the
+                // double range (all partial sums vanish): the block needs
+                // neither sums nor reduction
+                if (full) advance_steps<R, SPIN, true, kAdjChunk>(S, sT, b, n, c, lhi);
+                else advance_steps<R, SPIN, false, kAdjChunk>(S, sT, b, min(b + kAdjChunk, n), c, lhi);
+                if (!SEG || scaled) {  // without segments the branch is only taken while scaled
+                    adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
+                    scaled = leg_any_scaled<R, SPIN>(S);
+                }
                 continue;
             }
             if (full) {
@@ -607,7 +615,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
                         pb_r = fma(vm, fmr[r], pb_r);
                         pb_i = fma(vm, fmi[r], pb_i);
                     }
-                    if (c + t < lmax) leg_advance<R, SPIN>(S, sT[t]);
+                    if (c + t < lhi) leg_advance<R, SPIN>(S, sT[t]);
                 }
                 adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w, red, row, col);
             }
@@ -638,7 +646,7 @@ __global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
             const int t = b + u;
             // Im g~_l0 and Im c~_l0 vanish exactly for m = 0 (reality condition).
             const bool imag = h == 0 ? x == 1 : x == 0;
-            if (h < 2 && t < n && !(m == 0 && imag)) {
+            if (h < 2 && t < n && c + t >= lacc && !(m == 0 && imag)) {
                 const int64_t kk = base + c + t;
                 const double hP = (m == 0 ? 0.5 : 0.5 * a.mscale) * sT[t].w;
                 double val;
@@ -877,10 +885,16 @@ static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, doub
     LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
     a.items = p.d_leg_items_adj;
     a.nitems = p.n_leg_items_adj;
+    a.group *= p.leg_adj_lsegs;  // the l-segments of a (m, ring chunk) are consecutive items
     a.mscale = mscale;
     dim3 grid(p.n_leg_items_adj), block(64);
-    if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8>), grid, block, 0, st, a);
+    if (R == 2 && p.leg_adj_lsegs > 1) {
+        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8, true>), grid, block, 0, st, a);
+    } else {
+        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8, false>), grid, block, 0, st, a);
+    }
 }
 
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st) {

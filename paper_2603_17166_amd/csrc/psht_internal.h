@@ -91,7 +91,11 @@ void leg_table_host(LegTable &t, int lmax, int spin);
 std::shared_ptr<LegTable> leg_table_get(int lmax, int spin, Error &err);
 
 struct LegItem {
-    int32_t m, jb, je, pad;  // rings [jb, je) for this m
+    int32_t m, jb, je;  // rings [jb, je) for this m
+    // adjoint items of small plans: the item's outputs are the l in
+    // [lseg & 0xFFFF, (lseg >> 16) - 1] (its recurrence runs from the seed up to
+    // there); lseg = 0 means every l
+    int32_t lseg;
 };
 
 // ------------------------------------------------------------------- plan
@@ -117,6 +121,7 @@ struct psht_plan_s {
     psht::LegItem *d_leg_items_adj = nullptr;  // adjoint list (its own rings per lane and order)
     int n_leg_items_adj = 0;
     int leg_rings_per_item_adj = 0;
+    int leg_adj_lsegs = 1;  // l-segments per (m, ring chunk) in the adjoint list
     psht::LegItem *d_leg_items64 = nullptr;  // 64-ring chunks (batched-maps kernel)
     int n_leg_items64 = 0;
     std::shared_ptr<psht::LegTable> leg;
