@@ -147,6 +147,20 @@ psht_status psht_adjoint_grad(psht_plan plan, int nmaps, const void *map_grad, v
 psht_status psht_synth_grad(psht_plan plan, int nmaps, const void *alm_grad, void *map_grad,
                             void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* Synthesis without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same operation, layouts, stream semantics and errors as
+ * psht_synth, but the workspace is a static device array of
+ * PSHT_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends; the call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  A plan whose
+ * nmaps * workspace_bytes_per_map exceeds that size is rejected with
+ * PSHT_ERR_WORKSPACE before anything is launched.  All calls on one GPU share
+ * the array: calls that overlap on one GPU (different streams or threads)
+ * race; the caller serialises them (one stream, or stream ordering). */
+#define PSHT_NOALLOC_SCRATCH_BYTES (64u << 20)
+psht_status psht_synth_noalloc(psht_plan plan, int nmaps, const void *alm, void *map, void *hip_stream);
+
 /* Free the plan's device memory.  The caller must synchronise every stream
  * that still runs work of this plan first.  NULL is a no-op. */
 void psht_plan_destroy(psht_plan plan);

@@ -20,6 +20,8 @@ PSHT_ERR_WORKSPACE = 5
 
 PREC = {"auto": 0, "fp32": 1, "fp64": 2}
 
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PSHT_NOALLOC_SCRATCH_BYTES
+
 STAGE_LEGENDRE_SYNTH = 1
 STAGE_LEGENDRE_ADJOINT = 2
 
@@ -27,7 +29,7 @@ STAGE_LEGENDRE_ADJOINT = 2
 EXPORTS = (
     "psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_destroy",
     "psht_last_error", "psht_plan_geometry", "psht_stage", "psht_fft", "psht_legendre_column",
-    "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad",
+    "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc",
 )
 
 STAGE_NAMES = ("leg_synth", "theta_synth", "phi_synth", "interp", "grid_zero", "spread", "phi_adj", "theta_adj",
@@ -77,6 +79,7 @@ def load() -> ctypes.CDLL:
     lib.psht_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_adjoint_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_synth_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.psht_synth_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.psht_plan_destroy.argtypes = [vp]
     lib.psht_plan_destroy.restype = None
     lib.psht_last_error.argtypes = []
@@ -90,7 +93,7 @@ def load() -> ctypes.CDLL:
     lib.psht_plan_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     for name in ("psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_geometry",
                  "psht_stage", "psht_fft", "psht_legendre_column", "psht_plan_set_timing", "psht_plan_timing",
-                 "psht_adjoint_grad", "psht_synth_grad"):
+                 "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

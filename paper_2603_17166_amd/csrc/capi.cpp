@@ -421,6 +421,8 @@ bool check_ws(const psht_plan_s &p, int nmaps, void *ws, size_t ws_bytes) {
 
 }  // namespace
 
+psht_status psht::set_error(psht_status code, const char *msg) { return fail(code, msg); }
+
 extern "C" {
 
 psht_status psht_plan_create(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
@@ -447,8 +449,12 @@ psht_status psht_plan_query(psht_plan plan, psht_plan_info *info) {
 
 namespace {
 
-psht_status synth_impl(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
-                       double mscale, void *hip_stream) {
+}  // namespace
+
+// Synthesis of nmaps maps with the given workspace (shared by psht_synth,
+// psht_synth_grad and the entry point without allocation).
+psht_status psht::synth_run(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
+                            double mscale, void *hip_stream) {
     if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
     if (nmaps < 0) return fail(PSHT_ERR_ARG, "nmaps < 0");
     if (nmaps > 0 && (!alm || (!map && plan->npts > 0))) return fail(PSHT_ERR_ARG, "alm or map is NULL");
@@ -491,6 +497,8 @@ psht_status synth_impl(psht_plan plan, int nmaps, const void *alm, void *map, vo
     return PSHT_OK;
 }
 
+namespace {
+
 psht_status adjoint_impl(psht_plan plan, int nmaps, const void *map, void *alm, void *workspace, size_t ws_bytes,
                          double mscale, void *hip_stream) {
     if (!plan) return fail(PSHT_ERR_ARG, "plan is NULL");
@@ -527,7 +535,7 @@ extern "C" {
 
 psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
                        void *hip_stream) {
-    return synth_impl(plan, nmaps, alm, map, workspace, ws_bytes, 1.0, hip_stream);
+    return psht::synth_run(plan, nmaps, alm, map, workspace, ws_bytes, 1.0, hip_stream);
 }
 
 psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm, void *workspace, size_t ws_bytes,
@@ -542,7 +550,7 @@ psht_status psht_adjoint_grad(psht_plan plan, int nmaps, const void *map_grad, v
 
 psht_status psht_synth_grad(psht_plan plan, int nmaps, const void *alm_grad, void *map_grad, void *workspace,
                             size_t ws_bytes, void *hip_stream) {
-    return synth_impl(plan, nmaps, alm_grad, map_grad, workspace, ws_bytes, 0.5, hip_stream);
+    return psht::synth_run(plan, nmaps, alm_grad, map_grad, workspace, ws_bytes, 0.5, hip_stream);
 }
 
 void psht_plan_destroy(psht_plan plan) { free_plan(plan); }

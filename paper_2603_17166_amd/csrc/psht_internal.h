@@ -171,6 +171,13 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
 hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, const void *in, void *out,
                            hipStream_t st);
 
+// Synthesis driver behind psht_synth / psht_synth_grad (mscale 1 / 0.5): validates
+// the arguments and the workspace size, then issues every stage on hip_stream.
+psht_status synth_run(psht_plan plan, int nmaps, const void *alm, void *map, void *workspace, size_t ws_bytes,
+                      double mscale, void *hip_stream);
+// Sets the calling thread's error text (psht_last_error) and returns code.
+psht_status set_error(psht_status code, const char *msg);
+
 // Plan-time point kernels.
 hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n, double *d_stats,
                               hipStream_t st);
