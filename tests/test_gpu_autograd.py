@@ -25,12 +25,18 @@ def say(*a):
     print(*a, flush=True)
 
 
-def _coords(lmax, spin, mmax, n, seed):
-    """n random (component, l, m, part) coordinates with l >= spin, m <= min(l, mmax); m = 0 only real."""
+def _coords(lmax, spin, mmax, n, seed, stratified=False):
+    """n random (component, l, m, part) coordinates with l >= spin, m <= min(l, mmax); m = 0 only real.
+    stratified: coordinate i draws m from the i-th of n equal bins of [0, mmax], so the set spans every order."""
     r = np.random.default_rng(seed)
     out = []
     while len(out) < n:
-        m = int(r.integers(0, mmax + 1))
+        if stratified:
+            i = len(out)
+            lo, hi = (i * (mmax + 1)) // n, max((i * (mmax + 1)) // n + 1, ((i + 1) * (mmax + 1)) // n)
+            m = int(r.integers(lo, hi))
+        else:
+            m = int(r.integers(0, mmax + 1))
         l = int(r.integers(max(m, spin), lmax + 1))
         part = 0 if m == 0 else int(r.integers(0, 2))
         out.append((int(r.integers(0, 2)), l, m, part))
@@ -154,7 +160,10 @@ def test_autograd_patch_lmax3000_full_size():
     rms = float(d0.abs().pow(2).mean().sqrt())
     d = d0 + torch.as_tensor(syn.complex_noise(w.npoints, 0.01 * rms, syn.SEED_MAP + 50 + w.seed_base), device="cuda")
     a0 = torch.as_tensor(w.alm(0), device="cuda")
-    coords = _coords(w.lmax, w.spin, min(plan.info["mmax"], 400), 20, 95)
+    # 20 coordinates whose orders span 0 .. mmax (one per twentieth of the range)
+    coords = _coords(w.lmax, w.spin, plan.info["mmax"], 20, 95, stratified=True)
+    say("autograd patch: orders checked %s (mmax %d)" % (sorted(c[2] for c in coords), plan.info["mmax"]))
+    assert max(c[2] for c in coords) >= 0.9 * plan.info["mmax"]
     err, g = _fd_check(plan, a0, d, coords, 2.0)
     say("autograd patch: finite-difference vs autograd, max rel %.2e" % err)
     assert err <= 1e-7

@@ -1,38 +1,34 @@
-"""Serving form on the GPU: every result of a served mix (continuous
-batching, overlapping slots) equals the same request run alone, within the
-stated tolerance, and agrees with the oracle."""
+"""Serving form on the GPU, over the whole served mix: discs of 2, 5, 10 and
+20 deg, lmax 512 .. 4096, spin 0 and 2, synthesis and adjoint (FP32,
+eps 1e-5).  Every served result (continuous batching, overlapping slots)
+equals the same request run alone within 10 eps, and for every (radius,
+lmax, spin) one synthesis and one adjoint are checked against stored oracle
+results (tests/golden/served_discs.npz: a 64-point synthesis subsample, and
+the adjoint of a map on 64 points at 2048 seeded coefficients)."""
 import math
+import os
 
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
-import oracle
 from paper_2603_17166_amd import synthetic as syn
 from paper_2603_17166_amd.plan import Plan
 from paper_2603_17166_amd.serve import PlanKey, Server, TorchExecutor, latency_stats, poisson_arrivals, run_open_loop
 
 pytestmark = pytest.mark.gpu
 EPS = 1e-5
+HERE = os.path.dirname(os.path.abspath(__file__))
+FIXTURE = os.path.join(HERE, "golden", "served_discs.npz")
 
 
 def say(*a):
     print(*a, flush=True)
 
 
-def _mix(n):
-    patches = {r: syn.served_patch(r) for r in (2.0, 5.0)}
-    specs = syn.served_mix(n, seed=77, radii=(2.0, 5.0), lmaxes=(512, 1024))
-    reqs = []
-    for radius, lmax, spin, op, seed in specs:
-        key = PlanKey("disc%g" % radius, lmax, spin, EPS, "fp32")
-        if op == "synth":
-            data = torch.as_tensor(syn.gaussian_alm(lmax, spin, seed), device="cuda")
-        else:
-            data = torch.as_tensor(syn.gaussian_map(patches[radius][0].shape[0], seed, np.complex64), device="cuda")
-        reqs.append((key, op, data))
-    return patches, reqs
+def _code(radius, lmax, spin):
+    return int(100 * radius) + lmax // 512 + spin
 
 
 def _rel(a, b):
@@ -41,13 +37,56 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_served_mix_equals_alone():
-    patches, specs = _mix(48)
-    say("served mix: %d requests over %d patches" % (len(specs), len(patches)))
+def _requests(patches, fx):
+    """Every (radius, lmax, spin, op) once with random data, plus, per
+    (radius, lmax, spin), the synthesis and the adjoint of the stored oracle
+    checks; shuffled with a fixed seed.  Entries: (key, op, data, check)."""
+    out = []
+    for r in syn.SERVED_RADII:
+        n = patches[r][0].shape[0]
+        for lmax in syn.SERVED_LMAX:
+            for spin in syn.SERVED_SPINS:
+                key = PlanKey("disc%g" % r, lmax, spin, EPS, "fp32")
+                c = _code(r, lmax, spin)
+                pre = "r%g_l%d_s%d_" % (r, lmax, spin)
+                out.append((key, "synth", torch.as_tensor(syn.gaussian_alm(lmax, spin, 6000 + c), device="cuda"),
+                            None))
+                out.append((key, "adjoint", torch.as_tensor(syn.gaussian_map(n, 6100 + c, np.complex64),
+                                                             device="cuda"), None))
+                out.append((key, "synth", torch.as_tensor(syn.gaussian_alm(lmax, spin, 5000 + c), device="cuda"),
+                            ("synth", fx[pre + "idx"], fx[pre + "synth"])))
+                g = np.zeros(n, dtype=np.complex64)
+                g[fx[pre + "idx"]] = fx[pre + "adj_in"]
+                out.append((key, "adjoint", torch.as_tensor(g, device="cuda"),
+                            ("adjoint", fx[pre + "adj_k"], fx[pre + "adj_out"])))
+    perm = syn.rng(77).permutation(len(out))
+    return [out[i] for i in perm]
+
+
+def _check_oracle(res, check, lmax):
+    kind, sel, ref = check
+    if kind == "synth":
+        got = res.cpu().numpy()[sel].astype(np.complex128)
+        return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    m, _ = syn.alm_m_l(lmax)
+    mk = m[sel]
+    got = res.cpu().numpy()[:, sel]
+    w = np.where(mk == 0, 1.0, 2.0)
+    g = np.where(mk == 0, got.real + 0j, got)
+    r = np.where(mk == 0, ref.real + 0j, ref)
+    return math.sqrt(float(np.sum(w * np.abs(g - r) ** 2)) / float(np.sum(w * np.abs(r) ** 2)))
+
+
+def test_served_mix_equals_alone_and_oracle():
+    fx = np.load(FIXTURE)
+    patches = {r: syn.served_patch(r) for r in syn.SERVED_RADII}
+    reqs_spec = _requests(patches, fx)
+    say("served mix: %d requests over %d patches, %d plan kinds" % (
+        len(reqs_spec), len(patches), len({k for k, _, _, _ in reqs_spec})))
     # alone: one plan per key, one request at a time, synchronised
     plans = {}
     alone = []
-    for key, op, data in specs:
+    for key, op, data, _ in reqs_spec:
         if key not in plans:
             th, ph = patches[float(key.patch[4:])]
             plans[key] = Plan(th, ph, key.lmax, key.spin, key.epsilon, key.precision)
@@ -62,8 +101,9 @@ def test_served_mix_equals_alone():
     ex = TorchExecutor(n_slots=4)
     for r, (th, ph) in patches.items():
         ex.add_patch("disc%g" % r, th, ph)
-    srv = Server(ex, memory_budget=16 << 30, n_slots=4, max_batch=4)
-    offs = poisson_arrivals(len(specs), 4000.0, 5)
+    srv = Server(ex, memory_budget=64 << 30, n_slots=4, max_batch=4)
+    specs = [(k, op, d) for k, op, d, _ in reqs_spec]
+    offs = poisson_arrivals(len(specs), 3000.0, 5)
     reqs = run_open_loop(srv, specs, offs)
     torch.cuda.synchronize()
     st = latency_stats(reqs)
@@ -71,20 +111,23 @@ def test_served_mix_equals_alone():
     assert all(r.error is None for r in reqs)
     assert srv.max_concurrent > 1
     assert any(r.batch_size > 1 for r in reqs)
-    worst = 0.0
+    worst, worst_at = 0.0, None
     for r, ref in zip(reqs, alone):
-        worst = max(worst, _rel(r.result, ref))
-    say("worst served-vs-alone rel L2 %.2e" % worst)
+        e = _rel(r.result, ref)
+        if e > worst:
+            worst, worst_at = e, (r.key, r.op)
+    say("worst served-vs-alone rel L2 %.2e at %s" % (worst, worst_at))
     assert worst <= 10 * EPS
 
-    # two of the served results against the oracle (synthesis on a subsample, adjoint in full)
-    for r in reqs:
-        if r.op == "synth" and r.key.lmax == 512:
-            th, ph = patches[float(r.key.patch[4:])]
-            idx = np.sort(np.random.default_rng(3).choice(th.shape[0], 200, replace=False))
-            ref = oracle.synth(r.data.cpu().numpy(), th[idx], ph[idx], r.key.lmax, r.key.spin)
-            err = float(np.linalg.norm(r.result.cpu().numpy()[idx] - ref) / np.linalg.norm(ref))
-            say("served synth vs oracle rel L2 %.2e" % err)
-            assert err <= 10 * EPS
-            break
+    checked = set()
+    worst_o = 0.0
+    for r, (_, _, _, check) in zip(reqs, reqs_spec):
+        if check is None:
+            continue
+        e = _check_oracle(r.result, check, r.key.lmax)
+        worst_o = max(worst_o, e)
+        checked.add((r.key.patch, r.key.lmax, r.key.spin, r.op))
+        assert e <= 10 * EPS, (r.key, r.op, e)
+    say("served vs stored oracle: %d (radius, lmax, spin, op) checked, worst rel L2 %.2e" % (len(checked), worst_o))
+    assert len(checked) == len(syn.SERVED_RADII) * len(syn.SERVED_LMAX) * len(syn.SERVED_SPINS) * 2
     srv.close()
