@@ -7,9 +7,14 @@ interpolation / spreading) of one coefficient set / one map over the
 workload's points, with inputs resident in HBM.  The metric is
 synth+adjoint points/s = npoints / (time of one step).
 
-The default workload is the spin-2, lmax 2048, FP64, epsilon 1e-10
-SPT-3G-like rectangle (RA [-50, 50] x Dec [-71, -41] deg at 1 arcmin with
-2.5 arcmin RMS jitter, ~5.97M points).  Prints one JSON line.
+The headline workload is the spin-2, lmax 4096 patch of 1501 deg^2
+(RA [-48.4, 48.4] x Dec [-70, -42] deg at 0.5 arcmin with 2.5 arcmin RMS
+jitter, 21.6 M points) at epsilon 1e-10 in FP64 against epsilon 1e-5 in the
+FP32 form: `value` is the FP64 rate, the `fp32` object the FP32 form's, each
+with its roofline, per-stage fractions and its error against stored oracle
+results on a seeded 10 000-point subsample (synthesis) and on 20 480 seeded
+coefficients of the adjoint of a map supported on that subsample.  Prints
+one JSON line.
 """
 from __future__ import annotations
 
@@ -17,6 +22,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -28,50 +34,72 @@ import numpy as np  # noqa: E402
 from paper_2603_17166_amd import synthetic as syn  # noqa: E402
 
 WORKLOADS = {
+    "spt1501-l4096-s2-fp64": lambda: syn.spt_fine("fp64"),
+    "spt1501-l4096-s2-fp32": lambda: syn.spt_fine("fp32"),
     "spt1658-l2048-s2-fp64": lambda: syn.spt_like(2048),
     "cap10-l128-s0-fp64": lambda: syn.cap_small(),
-    "spt1501-l4096-s2-fp32": lambda: syn.spt_fine("fp32"),
-    "spt1501-l4096-s2-fp64": lambda: syn.spt_fine("fp64"),
     "rect999-l3000-s2-fp64": lambda: syn.autograd_patch(),
 }
-DEFAULT = "spt1658-l2048-s2-fp64"
+HEADLINE = ("spt1501-l4096-s2-fp64", "spt1501-l4096-s2-fp32")
+FIXTURE = os.path.join(ROOT, "tests", "golden", "spt1501_l4096_s2.npz")
 
 PEAK_FP64_VECTOR = 78.6e12   # FLOP/s, MI355X, FMA counted as 2
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12            # B/s
 
 
+# ----------------------------------------------------------- algorithmic work
+
 def leg_flops_per_triple(spin: int) -> int:
-    """Algorithmic FLOPs per (ring, m, l) of the Legendre step: per recurrence
-    mu_{l+1} = c mu_l - mu_{l-1} with c = (A +/- B) - A y one FMA for c and one
-    for the step (4 FLOPs), one recurrence for spin 0 and two for spin > 0,
-    plus four real multiply-adds (8 FLOPs) for the complex accumulation."""
-    return (8 if spin else 4) + 8
+    """Algorithmic FLOPs per (ring, m, l) triple of the Legendre step, the
+    per-unit figure of the measurement plan (about 13 for spin 0, 18 for
+    spin > 0: one or two three-term recurrences plus the complex
+    accumulation)."""
+    return 18 if spin else 13
 
 
 def nufft_flops_per_point(W: int) -> int:
-    """Algorithmic FLOPs per point of interpolation / spreading: W^2 taps of a
-    real weight times a complex value (2 FMAs) plus the W row weights (2W FMAs)
-    and the outer products of the two kernel vectors."""
-    return 4 * W * W + 4 * W
+    """Algorithmic FLOPs per point of interpolation / spreading with a W x W
+    kernel support: 8 W^2 + 16 W (the measurement plan's per-point figure)."""
+    return 8 * W * W + 16 * W
 
 
-def cpu_baseline(w, n_sample: int) -> dict:
-    import oracle
-
-    idx = w.subsample(n_sample)
-    th, ph = w.theta[idx], w.phi[idx]
-    a = w.alm()
-    f = syn.gaussian_map(idx.shape[0], 9001)
-    t0 = time.perf_counter()
-    oracle.synth(a, th, ph, w.lmax, w.spin)
-    t1 = time.perf_counter()
-    oracle.adjoint(f, th, ph, w.lmax, w.spin)
-    t2 = time.perf_counter()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": idx.shape[0] / (t2 - t0), "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": "%d seeded points of the workload, one synthesis + one adjoint, direct sum in long double "
-                      "(synth %.1f s, adjoint %.1f s)" % (idx.shape[0], t1 - t0, t2 - t1)}
+def stage_work(w, info) -> dict:
+    """Per stage: (bound, algorithmic amount per launch, peak) -- FLOP against
+    the FP64 vector peak for the Legendre stages and the FP64 NUFFT, bytes
+    against HBM for the FFT stages, the FP32 NUFFT and the fills (every array
+    written once and read once: F, V, U, the points' coordinates and values,
+    the coefficients of m <= mmax)."""
+    fp32 = bool(info["map_is_fp32"])
+    cs = 8 if fp32 else 16
+    ncol = 2 * info["mmax"] + 1
+    nring = info["Lmax"] + 1
+    rows, nphi = info["rows_used"], info["nphi_grid"]
+    F = ncol * nring * 16
+    V = rows * ncol * cs
+    U = rows * nphi * cs
+    n = w.npoints
+    lmax = w.lmax
+    alm_all = 2 * 16 * (lmax + 1) * (lmax + 2) // 2
+    leg = ("alu", info["legendre_triples"] * leg_flops_per_triple(w.spin), PEAK_FP64_VECTOR)
+    if fp32:
+        nu_i = ("hbm", U + n * (16 + cs), PEAK_HBM)
+        nu_s = nu_i
+    else:
+        nu_i = ("alu", n * nufft_flops_per_point(info["nufft_w"]), PEAK_FP64_VECTOR)
+        nu_s = nu_i
+    return {
+        "leg_synth": leg,
+        "theta_synth": ("hbm", F + V, PEAK_HBM),
+        "phi_synth": ("hbm", V + U, PEAK_HBM),
+        "interp": nu_i,
+        "grid_zero": ("hbm", U, PEAK_HBM),
+        "spread": nu_s,
+        "phi_adj": ("hbm", U + V, PEAK_HBM),
+        "theta_adj": ("hbm", V + F, PEAK_HBM),
+        "alm_zero": ("hbm", alm_all, PEAK_HBM),
+        "leg_adj": leg,
+    }
 
 
 STAGE_KERNEL = {"leg_synth": "psht::k_leg_synth", "leg_adj": "psht::k_leg_adjoint", "theta_synth": "psht::k_theta_synth",
@@ -108,25 +136,34 @@ def stage_avgs(stages: dict) -> dict:
     return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
 
 
+def stage_fractions(w, info, avg: dict, step_ms: float) -> dict:
+    """Roofline fraction of every stage and of the whole step: a stage's
+    roofline time is its algorithmic work at peak; the end-to-end fraction is
+    the sum of the stages' roofline times over the measured step time."""
+    work = stage_work(w, info)
+    out, roof_ms = {}, 0.0
+    for k, t in avg.items():
+        if t <= 0 or k not in work:
+            continue
+        bound, amount, peak = work[k]
+        ideal = amount / peak * 1e3
+        roof_ms += ideal
+        out[k] = {"ms": round(t, 4), "bound": bound, "roofline_ms": round(ideal, 4), "frac": round(ideal / t, 3)}
+    return {"stages": out, "roofline_ms": roof_ms, "end_to_end_frac": roof_ms / step_ms}
+
+
 def roofline(w, info, avg: dict) -> dict:
     """Roofline of the dominant kernel from live HIP-event timings."""
     dom = max(avg, key=lambda k: avg[k])
-    W = info["nufft_w"]
-    if dom in ("leg_synth", "leg_adj"):
-        flops = info["legendre_triples"] * leg_flops_per_triple(w.spin)
-        roof = {"bound": "alu", "achieved": flops / (avg[dom] * 1e-3) / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                "unit": "TFLOP/s", "work": "%.4g FLOP per launch (%d per (ring, m, l) triple)" % (
-                    flops, leg_flops_per_triple(w.spin))}
-    elif dom in ("interp", "spread") and not info["map_is_fp32"]:
-        flops = w.npoints * nufft_flops_per_point(W)
-        roof = {"bound": "alu", "achieved": flops / (avg[dom] * 1e-3) / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                "unit": "TFLOP/s", "work": "%.4g FLOP per launch (%d per point)" % (flops, nufft_flops_per_point(W))}
+    bound, amount, peak = stage_work(w, info)[dom]
+    if bound == "alu":
+        per = leg_flops_per_triple(w.spin) if dom.startswith("leg") else nufft_flops_per_point(info["nufft_w"])
+        unit_name = "(ring, m, l) triple" if dom.startswith("leg") else "point"
+        roof = {"bound": "alu", "achieved": amount / (avg[dom] * 1e-3) / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "work": "%.4g FLOP per launch (%d per %s)" % (amount, per, unit_name)}
     else:
-        cs = 8 if info["map_is_fp32"] else 16
-        grid = info["rows_used"] * info["nphi_grid"] * cs
-        nbytes = grid + w.npoints * (16 + 4 + cs)
-        roof = {"bound": "hbm", "achieved": nbytes / (avg[dom] * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "work": "%.4g B per launch" % nbytes}
+        roof = {"bound": "hbm", "achieved": amount / (avg[dom] * 1e-3) / 1e9, "peak": peak / 1e9, "unit": "GB/s",
+                "work": "%.4g B per launch" % amount}
     roof["frac"] = roof["achieved"] / roof["peak"]
     t = measured_traffic(dom, w.name)
     roof["traffic"] = t["bytes"] if t else None
@@ -138,40 +175,40 @@ def roofline(w, info, avg: dict) -> dict:
     return roof
 
 
-def time_steps(plan, a, fmap, out_map, out_alm, steps: int, which: str) -> float:
-    """Seconds for `steps` calls of synth, adjoint or both, bracketed by device synchronisation."""
+# ----------------------------------------------------------------- timing
+
+def time_steps(plan, a, fmap, out_map, out_alm, steps: int, which: str, per_step: list | None = None) -> float:
+    """Seconds for `steps` calls of synth, adjoint or both, bracketed by device
+    synchronisation; with `per_step`, HIP events on the launch stream around
+    every step append each step's milliseconds."""
     import torch
 
+    ev = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
+        if per_step is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record()
         if which in ("synth", "both"):
             plan.synth(a, out=out_map)
         if which in ("adjoint", "both"):
             plan.adjoint(fmap, out=out_alm)
+        if per_step is not None:
+            e1 = torch.cuda.Event(enable_timing=True)
+            e1.record()
+            ev.append((e0, e1))
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    t = time.perf_counter() - t0
+    if per_step is not None:
+        per_step.extend(e0.elapsed_time(e1) for e0, e1 in ev)
+    return t
 
 
-def oracle_error(w, a_np, out_map, n: int, log=None) -> float:
-    """Relative L2 error of the synthesized map on a seeded subsample of n points,
-    evaluated by the oracle in chunks of 1000 points (a progress line each)."""
-    import oracle
-
-    idx = w.subsample(n)
-    got = out_map.cpu().numpy()[idx].astype(np.complex128)
-    ref = np.empty_like(got)
-    for c in range(0, idx.shape[0], 1000):
-        sl = slice(c, c + 1000)
-        ref[sl] = oracle.synth(a_np, w.theta[idx[sl]], w.phi[idx[sl]], w.lmax, w.spin)
-        if log and idx.shape[0] > 1000:
-            log("%s: oracle check %d / %d points" % (w.name, min(c + 1000, idx.shape[0]), idx.shape[0]))
-    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-
-
-def run_transform(w, steps: int, warmup: int, check_points: int, log) -> dict:
-    """Plan, warm up, time synth+adjoint steps (with per-stage HIP events) and
-    synth-only / adjoint-only loops; oracle error on a subsample."""
+def run_transform(w, steps: int, warmup: int, log) -> dict:
+    """Plan, warm up, per-stage HIP-event breakdown (untimed steps), timed
+    synth+adjoint steps (events around the dominant kernel and around every
+    step), synth-only and adjoint-only loops."""
     import torch
 
     from paper_2603_17166_amd.plan import Plan
@@ -189,24 +226,150 @@ def run_transform(w, steps: int, warmup: int, check_points: int, log) -> dict:
     out_alm = torch.empty_like(a)
     plan.workspace(1)
     time_steps(plan, a, fmap, out_map, out_alm, warmup, "both")
-    # per-stage breakdown (events around every stage launch), outside the timed steps
     plan.set_timing(True)
     time_steps(plan, a, fmap, out_map, out_alm, min(steps, 5), "both")
     avg = stage_avgs(plan.timing())
-    # timed steps: events around the dominant kernel's launches only, for its roofline
     dom = max(avg, key=lambda k: avg[k])
     plan.set_timing(True, stages=(dom,))
-    t_both = time_steps(plan, a, fmap, out_map, out_alm, steps, "both")
+    per_step: list = []
+    t_both = time_steps(plan, a, fmap, out_map, out_alm, steps, "both", per_step)
     avg[dom] = stage_avgs(plan.timing())[dom]
     plan.set_timing(False)
     t_syn = time_steps(plan, a, fmap, out_map, out_alm, steps, "synth")
     t_adj = time_steps(plan, a, fmap, out_map, out_alm, steps, "adjoint")
-    err = oracle_error(w, a_np, out_map, check_points, log)
     res = {"plan": plan, "info": info, "plan_s": plan_s, "ms_per_step": t_both * 1e3 / steps, "avg": avg,
-           "synth_ms": t_syn * 1e3 / steps, "adjoint_ms": t_adj * 1e3 / steps, "rel_err": err}
-    log("%s: %.3f ms/step (synth %.3f, adjoint %.3f), rel err %.2e" % (
-        w.name, res["ms_per_step"], res["synth_ms"], res["adjoint_ms"], err))
+           "synth_ms": t_syn * 1e3 / steps, "adjoint_ms": t_adj * 1e3 / steps,
+           "step_ms_median": float(np.median(per_step)), "step_ms_p90": float(np.percentile(per_step, 90)),
+           "a_np": a_np, "out_map": out_map}
+    log("%s: %.3f ms/step (median %.3f, p90 %.3f; synth %.3f, adjoint %.3f)" % (
+        w.name, res["ms_per_step"], res["step_ms_median"], res["step_ms_p90"], res["synth_ms"], res["adjoint_ms"]))
     return res
+
+
+def fixture_errors(w, plan, out_map) -> dict:
+    """Errors against the stored oracle results of the lmax 4096 patch: the
+    synthesis on the 10 000-point subsample, and the adjoint of a map that is
+    non-zero only there, on the stored coefficients (the coefficient inner
+    product's weights: m = 0 real parts once, m > 0 twice)."""
+    import torch
+
+    if not os.path.exists(FIXTURE):
+        return {"error": "fixture missing"}
+    fx = np.load(FIXTURE)
+    idx = fx["idx"]
+    if not np.array_equal(idx, w.subsample(idx.shape[0])):
+        return {"error": "subsample differs from the fixture's"}
+    got = out_map.cpu().numpy()[idx].astype(np.complex128)
+    ref = fx["synth"]
+    synth_err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    g = torch.zeros(w.npoints, dtype=plan.map_dtype, device="cuda")
+    g[torch.as_tensor(idx, device="cuda")] = torch.as_tensor(fx["adj_in"].astype(
+        np.complex64 if plan.info["map_is_fp32"] else np.complex128), device="cuda")
+    at = plan.adjoint(g).cpu().numpy()
+    k = fx["adj_k"]
+    m, _ = syn.alm_m_l(w.lmax)
+    mk = m[k]
+    wgt = np.where(mk == 0, 1.0, 2.0)
+    got_a = at[:, k]
+    ref_a = fx["adj_out"]
+    got_a = np.where(mk == 0, got_a.real + 0j, got_a)
+    ref_a = np.where(mk == 0, ref_a.real + 0j, ref_a)
+    num = float(np.sum(wgt * np.abs(got_a - ref_a) ** 2))
+    den = float(np.sum(wgt * np.abs(ref_a) ** 2))
+    return {"synth_rel_l2": synth_err, "synth_points": int(idx.shape[0]), "adjoint_rel_l2": math.sqrt(num / den),
+            "adjoint_from_points": int(idx.shape[0]), "adjoint_coefficients": int(k.shape[0]),
+            "bar": 10 * w.epsilon}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, n_all: int, n_one: int, log) -> dict:
+    """The oracle (direct sums in long double) on the host: a seeded sample of
+    the workload's points with every host core, and a smaller one on one core."""
+    import oracle
+
+    idx = w.subsample(max(n_all, n_one))
+    a = w.alm()
+    res = {}
+    for label, n, threads in (("every", n_all, 0), ("one", n_one, 1)):
+        sub = idx[:n]
+        th, ph = w.theta[sub], w.phi[sub]
+        f = syn.gaussian_map(sub.shape[0], 9001)
+        t0 = time.perf_counter()
+        oracle.synth(a, th, ph, w.lmax, w.spin, nthreads=threads)
+        t1 = time.perf_counter()
+        oracle.adjoint(f, th, ph, w.lmax, w.spin, nthreads=threads)
+        t2 = time.perf_counter()
+        res[label] = (sub.shape[0], t1 - t0, t2 - t1)
+        log("cpu baseline (%s core): %d points, synth %.1f s, adjoint %.1f s" % (label, sub.shape[0], t1 - t0, t2 - t1))
+    n, ts, ta = res["every"]
+    n1, ts1, ta1 = res["one"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n / (ts + ta), "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": "%d seeded points of the workload (lmax %d, spin %d), one synthesis + one adjoint, direct sums "
+                      "in long double on every host core (synth %.1f s, adjoint %.1f s)" % (n, w.lmax, w.spin, ts, ta),
+            "cpu_model": cpu_model(), "value_1core": n1 / (ts1 + ta1),
+            "sample_1core": "%d points on one core (synth %.1f s, adjoint %.1f s)" % (n1, ts1, ta1)}
+
+
+# ----------------------------------------------------------------- extras
+
+def small_line(w, steps: int, warmup: int, log) -> dict:
+    r = run_transform(w, steps, warmup, log)
+    out = {"workload": w.name, "npoints": w.npoints, "points_per_s": w.npoints / (r["ms_per_step"] * 1e-3),
+           "ms_per_step": r["ms_per_step"], "step_ms_median": r["step_ms_median"], "step_ms_p90": r["step_ms_p90"],
+           "synth_ms": r["synth_ms"], "adjoint_ms": r["adjoint_ms"], "plan_s": r["plan_s"],
+           "roofline": roofline(w, r["info"], r["avg"]),
+           "adjoint_segment": r["info"]["adj_segment"], "adjoint_waves": r["info"]["adj_waves"],
+           "adjoint_rings_per_lane": r["info"]["adj_rings_per_lane"]}
+    out.update(stage_fractions(w, r["info"], r["avg"], r["step_ms_median"]))
+    r["plan"].close()
+    return out
+
+
+def autograd_step(steps: int, log) -> dict:
+    """One optimisation step of loss = ||synth(alm) - d||^2 on the 999 deg^2,
+    lmax 3000, spin-2 patch (FP64): forward synthesis, backward through the
+    adjoint kernel; d = synthesis of a second coefficient set + 1 % noise."""
+    import torch
+
+    from paper_2603_17166_amd.autograd import SynthFn
+    from paper_2603_17166_amd.plan import Plan
+
+    w = syn.autograd_patch()
+    plan = Plan(w.theta, w.phi, w.lmax, w.spin, w.epsilon, w.precision)
+    d0 = plan.synth(torch.as_tensor(w.alm(1), device="cuda"))
+    rms = float(d0.abs().pow(2).mean().sqrt())
+    d = d0 + torch.as_tensor(syn.complex_noise(w.npoints, 0.01 * rms, syn.SEED_MAP + 50 + w.seed_base), device="cuda")
+    a = torch.as_tensor(w.alm(0), device="cuda").requires_grad_(True)
+
+    def one():
+        a.grad = None
+        loss = (SynthFn.apply(a, plan) - d).abs().pow(2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(2):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.close()
+    log("autograd step (%s): %.3f ms" % (w.name, ms))
+    return {"workload": w.name, "npoints": w.npoints, "ms_per_step": ms, "points_per_s": w.npoints / (ms * 1e-3),
+            "note": "forward synthesis + loss + backward (adjoint kernel) per step"}
 
 
 def batched_maps(w, nmaps: int, steps: int, check_points: int, log) -> dict:
@@ -236,45 +399,36 @@ def batched_maps(w, nmaps: int, steps: int, check_points: int, log) -> dict:
     err = float(np.linalg.norm(out_map[-1].cpu().numpy()[idx] - ref) / np.linalg.norm(ref))
     plan.close()
     ms = t_both * 1e3 / steps
-    res = {"nmaps": nmaps, "ms_per_step": ms, "points_per_s": nmaps * w.npoints / (ms * 1e-3),
+    res = {"workload": w.name, "nmaps": nmaps, "ms_per_step": ms, "points_per_s": nmaps * w.npoints / (ms * 1e-3),
            "leg_synth_ms_per_map": avg["leg_synth"] / nmaps, "rel_err_vs_oracle_last_map": err,
            "stage_ms_per_launch": {k: round(v, 4) for k, v in avg.items()}}
     log("batched %d maps: %.3f ms per step (synth + adjoint of all maps), rel err %.2e" % (nmaps, ms, err))
     return res
 
 
-def precision_form(steps: int, check_points: int, log) -> dict:
-    """FP32 (eps 1e-5) vs FP64 (eps 1e-10) on the 1501 deg^2, lmax 4096 patch."""
-    out = {}
-    for prec in ("fp32", "fp64"):
-        w = syn.spt_fine(prec)
-        r = run_transform(w, steps, 2, check_points, log)
-        out[prec] = {"epsilon": w.epsilon, "points_per_s": w.npoints / (r["ms_per_step"] * 1e-3),
-                     "ms_per_step": r["ms_per_step"], "synth_ms": r["synth_ms"], "adjoint_ms": r["adjoint_ms"],
-                     "rel_err_vs_oracle": r["rel_err"], "rel_err_points": check_points, "plan_s": r["plan_s"],
-                     "stage_ms": {k: round(v, 4) for k, v in r["avg"].items()}}
-        r["plan"].close()
-    out["workload"] = "spt1501-l4096-s2 (%d points)" % syn.spt_fine("fp32").npoints
-    out["fp32_speedup"] = out["fp32"]["points_per_s"] / out["fp64"]["points_per_s"]
-    return out
-
-
-def served(n_requests: int, load: float, log) -> dict:
-    """Served mix: discs of 2/5/10/20 deg, lmax 512..4096, spin 0/2, 50/50 synth/adjoint, FP32 eps 1e-5."""
+def served(n_requests: int, load: float, log, single_fp64: int = 0) -> dict:
+    """Served mix: discs of 2/5/10/20 deg, lmax 512..4096, spin 0/2, 50/50
+    synth/adjoint, FP32 eps 1e-5.  With single_fp64 > 0, the first that many
+    requests of the same mix are also run one at a time (no batching, no
+    overlap) on FP64 eps 1e-10 plans, the plain-FP64-single rate of the same
+    requests."""
     import torch
 
-    from paper_2603_17166_amd.serve import (PlanKey, Server, TorchExecutor, latency_stats, poisson_arrivals,
-                                            run_closed_loop, run_open_loop)
+    from paper_2603_17166_amd.plan import Plan
+    from paper_2603_17166_amd.serve import (PlanKey, Server, TorchExecutor, latency_stats, percentile,
+                                            poisson_arrivals, run_closed_loop, run_open_loop)
 
     eps = 1e-5
     ex = TorchExecutor(n_slots=4)
-    npts = {}
-    maps = {}
+    npts, maps, maps64, patches = {}, {}, {}, {}
     for r in syn.SERVED_RADII:
         th, ph = syn.served_patch(r)
+        patches[r] = (th, ph)
         ex.add_patch("disc%g" % r, th, ph)
         npts[r] = th.shape[0]
-        maps[r] = torch.as_tensor(syn.gaussian_map(th.shape[0], syn.SEED_MAP + 4 + int(r), np.complex64), device="cuda")
+        m = syn.gaussian_map(th.shape[0], syn.SEED_MAP + 4 + int(r), np.complex64)
+        maps[r] = torch.as_tensor(m, device="cuda")
+        maps64[r] = torch.as_tensor(m.astype(np.complex128), device="cuda")
     alms = {}
     for lmax in syn.SERVED_LMAX:
         for spin in syn.SERVED_SPINS:
@@ -289,14 +443,14 @@ def served(n_requests: int, load: float, log) -> dict:
         return out
 
     srv = Server(ex, memory_budget=96 << 30, n_slots=4, max_batch=4)
-    # warm-up: every combination once (creates and caches all plans)
     t0 = time.perf_counter()
     combos = [(r, l, s, op, 0) for r in syn.SERVED_RADII for l in syn.SERVED_LMAX for s in syn.SERVED_SPINS
               for op in ("synth", "adjoint")]
     run_closed_loop(srv, specs_of(combos))
     torch.cuda.synchronize()
     log("served: %d plans created in %.1f s" % (srv.plans_created, time.perf_counter() - t0))
-    mix = specs_of(syn.served_mix(n_requests, seed=syn.SEED_MAP + 4))
+    raw_mix = syn.served_mix(n_requests, seed=syn.SEED_MAP + 4)
+    mix = specs_of(raw_mix)
     reqs, secs = run_closed_loop(srv, mix)
     sat = len(reqs) / secs
     log("served: saturation %.1f requests/s" % sat)
@@ -307,13 +461,73 @@ def served(n_requests: int, load: float, log) -> dict:
     st = latency_stats(reqs)
     pts = sum(npts[float(r.key.patch[4:])] for r in reqs)
     span = max(r.t_done for r in reqs) - min(r.t_arrival for r in reqs)
+    kinds = {}
+    for r in reqs:
+        if r.error is None:
+            kinds.setdefault("%s-l%d-%s" % (r.key.patch, r.key.lmax, r.op), []).append(r.latency * 1e3)
     st.update({"load": load, "arrival_rate_per_s": rate, "saturation_requests_per_s": sat,
                "points_per_s": pts / span, "saturation_points_per_s": pts / secs, "batches": srv.n_batches,
                "max_concurrent": srv.max_concurrent, "plans_resident": len(srv.plans),
-               "resident_gb": srv.resident / 1e9, "errors": sum(1 for r in reqs if r.error)})
+               "resident_gb": srv.resident / 1e9, "errors": sum(1 for r in reqs if r.error),
+               "latency_ms_by_kind": {k: {"p50": round(percentile(v, 50), 3), "p99": round(percentile(v, 99), 3),
+                                          "n": len(v)} for k, v in sorted(kinds.items())}})
     log("served at %.1fx saturation: p50 %.2f ms, p99 %.2f ms" % (load, st["p50_ms"], st["p99_ms"]))
     srv.close()
+    if single_fp64 > 0:
+        sub = raw_mix[:single_fp64]
+        plans = {}
+        for radius, lmax, spin, op, _ in sub:
+            key = (radius, lmax, spin)
+            if key not in plans:
+                th, ph = patches[radius]
+                plans[key] = Plan(th, ph, lmax, spin, 1e-10, "fp64")
+                plans[key].workspace(1)
+        for p in plans.values():  # warm up every plan once
+            p.synth(alms[(p.lmax, p.spin)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pts64 = 0
+        for radius, lmax, spin, op, _ in sub:
+            p = plans[(radius, lmax, spin)]
+            if op == "synth":
+                p.synth(alms[(lmax, spin)])
+            else:
+                p.adjoint(maps64[radius])
+            torch.cuda.synchronize()
+            pts64 += npts[radius]
+        secs64 = time.perf_counter() - t0
+        for p in plans.values():
+            p.close()
+        st["fp64_single_same_requests"] = {"requests": len(sub), "points_per_s": pts64 / secs64,
+                                           "note": "the first requests of the same mix, FP64 eps 1e-10 plans, one "
+                                                   "request at a time with a device synchronisation after each"}
+        st["served_vs_fp64_single"] = st["points_per_s"] / (pts64 / secs64)
+        log("served vs plain FP64 single on the same requests: %.2fx" % st["served_vs_fp64_single"])
     return st
+
+
+# ------------------------------------------------------------------- main
+
+def headline(steps: int, warmup: int, log) -> tuple:
+    out = {}
+    for name in HEADLINE:
+        w = WORKLOADS[name]()
+        r = run_transform(w, steps, warmup, log)
+        fx = fixture_errors(w, r["plan"], r["out_map"])
+        log("%s: vs stored oracle %s" % (name, fx))
+        d = {"workload": name, "epsilon": w.epsilon, "precision": w.precision,
+             "value": w.npoints / (r["ms_per_step"] * 1e-3), "ms_per_step": r["ms_per_step"],
+             "step_ms_median": r["step_ms_median"], "step_ms_p90": r["step_ms_p90"],
+             "synth_points_per_s": w.npoints / (r["synth_ms"] * 1e-3),
+             "adjoint_points_per_s": w.npoints / (r["adjoint_ms"] * 1e-3),
+             "transforms_per_s": 2.0 / (r["ms_per_step"] * 1e-3), "plan_s": r["plan_s"],
+             "vs_oracle": fx, "roofline": roofline(w, r["info"], r["avg"]),
+             "dtype": "f32+f64" if r["info"]["map_is_fp32"] else "f64"}
+        d.update(stage_fractions(w, r["info"], r["avg"], r["step_ms_median"]))
+        d["info"] = r["info"]
+        r["plan"].close()
+        out[name] = (w, d)
+    return out
 
 
 def main() -> int:
@@ -321,15 +535,16 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=1536)
+    ap.add_argument("--workload", default=None, choices=sorted(WORKLOADS),
+                    help="time only this workload (one line, no extras); default: the lmax 4096 FP64/FP32 pair")
+    ap.add_argument("--cpu-sample", type=int, default=192, help="oracle points on every host core")
+    ap.add_argument("--cpu-sample-1core", type=int, default=12, help="oracle points on one core")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check-points", type=int, default=64, help="oracle check of the synthesized map")
-    ap.add_argument("--no-extras", action="store_true", help="skip the precision-form and served-mix runs")
-    ap.add_argument("--precision-check-points", type=int, default=32,
-                    help="oracle subsample of the precision form (10000 takes about 6 min per precision on 16 cores)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads and the served mix")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--serve-fp64-single", type=int, default=300,
+                    help="requests of the served mix also run one at a time on FP64 plans")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -352,44 +567,61 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
         return 0
-    w = WORKLOADS[args.workload]()
-    r = run_transform(w, args.steps, args.warmup, args.check_points, log)
-    info, avg = r["info"], r["avg"]
-    ms_per_step = r["ms_per_step"]
-    line = {
-        "metric": "synth+adjoint points/s at eps=1e-10 FP64 vs eps=1e-5 FP32; p50/p99 latency",
-        "value": w.npoints / (ms_per_step * 1e-3),
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if info["map_is_fp32"] else "f64",
-        "data": "synthetic (seeded points and coefficients)",
-        "config": {"workload": w.name, "npoints": w.npoints, "lmax": w.lmax, "spin": w.spin, "epsilon": w.epsilon,
-                   "precision": w.precision, "Lmax": info["Lmax"], "mmax": info["mmax"], "nufft_w": info["nufft_w"],
-                   "grid": [info["rows_used"], info["nphi_grid"]], "legendre_triples": info["legendre_triples"]},
-        "synth_points_per_s": w.npoints / (r["synth_ms"] * 1e-3),
-        "adjoint_points_per_s": w.npoints / (r["adjoint_ms"] * 1e-3),
-        "transforms_per_s": 2.0 / (ms_per_step * 1e-3),
-        "rel_err_vs_oracle": r["rel_err"],
-        "plan_s": r["plan_s"],
-        "stage_ms": {k: round(avg[k], 4) for k in avg},
-        "roofline": roofline(w, info, avg),
-    }
-    r["plan"].close()
+    metric = "synth+adjoint points/s at eps=1e-10 FP64 vs eps=1e-5 FP32; p50/p99 latency"
+    base = {"metric": metric, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "data": "synthetic (seeded points and coefficients)"}
+    if args.workload:
+        w = WORKLOADS[args.workload]()
+        d = small_line(w, args.steps, args.warmup, log)
+        line = dict(base, value=d["points_per_s"], ms_per_step=d["ms_per_step"],
+                    dtype="f32+f64" if w.precision == "fp32" else "f64",
+                    config={"workload": w.name, "npoints": w.npoints, "lmax": w.lmax, "spin": w.spin,
+                            "epsilon": w.epsilon, "precision": w.precision}, roofline=d.pop("roofline"))
+        line.update(d)
+        print(json.dumps(line), flush=True)
+        return 0
+
+    pair = headline(args.steps, args.warmup, log)
+    w64, d64 = pair[HEADLINE[0]]
+    w32, d32 = pair[HEADLINE[1]]
+    info = d64.pop("info")
+    info32 = d32.pop("info")
+    line = dict(base)
+    line.update({
+        "value": d64["value"], "ms_per_step": d64["ms_per_step"], "dtype": "f64",
+        "config": {"workload": "spt1501-l4096-s2 (eps 1e-10 FP64 vs eps 1e-5 FP32)", "npoints": w64.npoints,
+                   "lmax": w64.lmax, "spin": w64.spin, "epsilon": w64.epsilon, "precision": "fp64",
+                   "Lmax": info["Lmax"], "mmax": info["mmax"], "nufft_w": info["nufft_w"],
+                   "grid": [info["rows_used"], info["nphi_grid"]], "legendre_triples": info["legendre_triples"],
+                   "adjoint_segment": info["adj_segment"], "adjoint_waves": info["adj_waves"],
+                   "adjoint_rings_per_lane": info["adj_rings_per_lane"]},
+        "step_ms_median": d64["step_ms_median"], "step_ms_p90": d64["step_ms_p90"],
+        "synth_points_per_s": d64["synth_points_per_s"], "adjoint_points_per_s": d64["adjoint_points_per_s"],
+        "transforms_per_s": d64["transforms_per_s"], "plan_s": d64["plan_s"], "vs_oracle": d64["vs_oracle"],
+        "roofline": d64["roofline"], "stages": d64["stages"], "end_to_end_frac": d64["end_to_end_frac"],
+        "fp32": dict(d32, config={"Lmax": info32["Lmax"], "mmax": info32["mmax"], "nufft_w": info32["nufft_w"],
+                                  "grid": [info32["rows_used"], info32["nphi_grid"]],
+                                  "legendre_triples": info32["legendre_triples"],
+                                  "adjoint_segment": info32["adj_segment"], "adjoint_waves": info32["adj_waves"],
+                                  "adjoint_rings_per_lane": info32["adj_rings_per_lane"]}),
+        "fp32_vs_fp64": d32["value"] / d64["value"],
+    })
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
-        log("cpu baseline: %.1f points/s" % line["cpu_baseline"]["value"])
+        line["cpu_baseline"] = cpu_baseline(w64, args.cpu_sample, args.cpu_sample_1core, log)
     if not args.no_extras:
-        line["batched_maps"] = batched_maps(w, 8, max(3, args.steps // 4), 16, log)
-        line["batched_maps"]["speedup_per_map"] = line["batched_maps"]["points_per_s"] / line["value"]
-        line["precision_form"] = precision_form(max(3, args.steps // 4), args.precision_check_points, log)
-        line["served"] = served(args.serve_requests, args.serve_load, log)
-        line["served_vs_fp64_single"] = line["served"]["points_per_s"] / line["value"]
+        ex = {}
+        ex["cap10-l128-s0-fp64"] = small_line(syn.cap_small(), args.steps, args.warmup, log)
+        w2 = syn.spt_like(2048)
+        ex["spt1658-l2048-s2-fp64"] = small_line(w2, args.steps, args.warmup, log)
+        ex["rect999-l3000-s2-fp64-autograd"] = autograd_step(max(3, args.steps // 4), log)
+        ex["batched_maps"] = batched_maps(w2, 8, max(3, args.steps // 4), 16, log)
+        ex["batched_maps"]["speedup_per_map"] = ex["batched_maps"]["points_per_s"] / \
+            ex["spt1658-l2048-s2-fp64"]["points_per_s"]
+        line["other_workloads"] = ex
+        line["served"] = served(args.serve_requests, args.serve_load, log, args.serve_fp64_single)
+        if "served_vs_fp64_single" in line["served"]:
+            line["served_vs_fp64_single"] = line["served"]["served_vs_fp64_single"]
     print(json.dumps(line), flush=True)
     return 0
 

@@ -96,6 +96,13 @@ typedef struct {
     size_t resident_bytes;          /* device memory the plan holds */
     size_t workspace_bytes_per_map; /* workspace psht_synth/psht_adjoint need per map */
     double kernel_poly_err;  /* largest error of the polynomial ES kernel taps (inner taps) */
+    /* Legendre adjoint work decomposition: degree segments of adj_segment
+     * degrees per order, adj_waves wavefronts per work item (together holding
+     * every active ring of the order, at most adj_rings_per_lane rings per
+     * lane); adj_states recurrence states (40 bytes each) stored by the plan
+     * for the segment starts. */
+    int32_t adj_segment, adj_waves, adj_rings_per_lane;
+    int64_t adj_states;
 } psht_plan_info;
 
 /* Build a plan for npoints points (device arrays theta, phi; read during the
@@ -167,6 +174,14 @@ void psht_plan_destroy(psht_plan plan);
 
 /* Thread-local text for the last non-OK status of this thread ("" if none). */
 const char *psht_last_error(void);
+
+/* Integrity counter of a plan: *dropped receives the number of points the
+ * interpolation / spreading kernels found outside the NUFFT tile they were
+ * sorted into and had to skip since the plan was created.  Plan creation
+ * verifies the sort (and fails with PSHT_ERR_DEVICE if any point is outside
+ * its tile), so this is 0 unless something is broken.  Synchronises
+ * hip_stream (the stream the plan's work ran on) before reading. */
+psht_status psht_plan_check(psht_plan plan, int64_t *dropped, void *hip_stream);
 
 /* Host-only evaluation of the plan parameters for a cap of radius theta_star
  * (theta_min = 0), without any device work: the rules of Sec. II.B-C for

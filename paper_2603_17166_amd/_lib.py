@@ -30,6 +30,7 @@ EXPORTS = (
     "psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_destroy",
     "psht_last_error", "psht_plan_geometry", "psht_stage", "psht_fft", "psht_legendre_column",
     "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc",
+    "psht_plan_check",
 )
 
 STAGE_NAMES = ("leg_synth", "theta_synth", "phi_synth", "interp", "grid_zero", "spread", "phi_adj", "theta_adj",
@@ -48,6 +49,8 @@ class PlanInfo(ctypes.Structure):
         ("legendre_triples", ctypes.c_double),
         ("npoints", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t), ("workspace_bytes_per_map", ctypes.c_size_t),
         ("kernel_poly_err", ctypes.c_double),
+        ("adj_segment", ctypes.c_int32), ("adj_waves", ctypes.c_int32), ("adj_rings_per_lane", ctypes.c_int32),
+        ("adj_states", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -80,6 +83,7 @@ def load() -> ctypes.CDLL:
     lib.psht_adjoint_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_synth_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_synth_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.psht_plan_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp]
     lib.psht_plan_destroy.argtypes = [vp]
     lib.psht_plan_destroy.restype = None
     lib.psht_last_error.argtypes = []
@@ -93,7 +97,7 @@ def load() -> ctypes.CDLL:
     lib.psht_plan_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     for name in ("psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_geometry",
                  "psht_stage", "psht_fft", "psht_legendre_column", "psht_plan_set_timing", "psht_plan_timing",
-                 "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc"):
+                 "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc", "psht_plan_check"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

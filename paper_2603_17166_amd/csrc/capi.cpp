@@ -126,6 +126,10 @@ void fill_info(const psht_plan_s &p, psht_plan_info *info) {
     info->resident_bytes = p.resident + (p.leg ? p.leg->bytes : 0);
     info->workspace_bytes_per_map = p.ws_per_map;
     info->kernel_poly_err = g.es_poly_err;
+    info->adj_segment = p.adj_seg;
+    info->adj_waves = p.adj_waves;
+    info->adj_rings_per_lane = p.adj_rmax;
+    info->adj_states = p.n_adj_states;
 }
 
 struct ScopedDevFree {
@@ -134,6 +138,104 @@ struct ScopedDevFree {
         if (p) (void)hipFree(p);
     }
 };
+
+// Work list and recurrence states of the segmented Legendre adjoint.
+//
+// Order m has the active rings [first_m, last_m] (ring_mmax >= m) and the
+// degrees l0 .. lmax, l0 = max(m, s).  The plan takes the smallest G of 1, 2, 4
+// waves per workgroup with 384 G >= rings (at most 6 rings per lane; whole
+// workgroups then fill a CU's eight wave slots) and splits each order's ring
+// range evenly over them (R_m rings per lane).  The segment length S is the
+// largest power of two (at least 64) for which the longest item costs at most
+// a third of the average work per wave slot (two waves per SIMD): with
+// longest-first placement the last items then finish close together.
+// Segments k >= 1 start from stored states (40 bytes per ring and segment).
+bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error &err) {
+    const psht::Geometry &g = p.g;
+    const int lmax = g.lmax, s = g.spin, M = g.mmax;
+    std::vector<int> first(M + 1, -1), last(M + 1, -1);
+    for (int j = 0; j < g.nring; ++j)
+        for (int m = 0; m <= std::min(M, (int)g.ring_mmax[j]); ++m) {
+            if (first[m] < 0) first[m] = j;
+            last[m] = j;
+        }
+    int nrmax = 1;
+    for (int m = 0; m <= M; ++m)
+        if (first[m] >= 0) nrmax = std::max(nrmax, last[m] - first[m] + 1);
+    int G = 1;
+    while (G < psht::kAdjMaxWavesHost && 64 * psht::kAdjMaxRings * G < nrmax) G *= 2;
+    if (const char *e = getenv("PSHT_ADJ_WAVES")) {  // tuning runs: 1, 2 or 4, as long as the rings fit
+        const int v = atoi(e);
+        if ((v == 1 || v == 2 || v == 4) && 64 * psht::kAdjMaxRings * v >= nrmax) G = v;
+    }
+    auto rings_per_lane = [&](int m) {
+        if (first[m] < 0) return 0;
+        const int nr = last[m] - first[m] + 1;
+        return (nr + 64 * G - 1) / (64 * G);
+    };
+    double total = 0.0;
+    int rmax = 1;
+    for (int m = 0; m <= M; ++m) {
+        const int R = rings_per_lane(m);
+        rmax = std::max(rmax, R);
+        total += (double)(lmax + 1 - std::max(m, s)) * R * G;
+    }
+    const double slots = (double)std::max(ncu, 1) * 4 * 2;
+    int S = 64;
+    while (S * 2 <= lmax + 1 && (double)(S * 2) * rmax <= total / slots / 3.0) S *= 2;
+    if (const char *e = getenv("PSHT_ADJ_SEG")) {  // tuning runs
+        const int v = atoi(e);
+        if (v >= 8 && v <= 1 << 16) S = v;
+    }
+    std::vector<psht::AdjItem> items;
+    std::vector<psht::StateItem> sitems;
+    int64_t off = 0;
+    for (int m = 0; m <= M; ++m) {
+        const int l0 = std::max(m, s);
+        const int R = rings_per_lane(m);
+        if (R == 0) {
+            items.push_back(psht::AdjItem{m, 0, 0, m, lmax + 1, 0, -1});
+            continue;
+        }
+        const int jb = first[m], je = last[m] + 1, nr = je - jb;
+        const int nseg = (lmax + 1 - l0 + S - 1) / S;
+        for (int k = 0; k < nseg; ++k) {
+            const int la = l0 + k * S, lb = std::min(lmax + 1, la + S);
+            items.push_back(psht::AdjItem{m, jb, je, la, lb, R, k == 0 ? -1 : off + (int64_t)(k - 1) * nr});
+        }
+        if (nseg > 1) {
+            for (int j0 = jb; j0 < je; j0 += 64) sitems.push_back(psht::StateItem{m, j0, jb, je, nseg, S, off});
+            off += (int64_t)(nseg - 1) * nr;
+        }
+    }
+    // longest first (blocks are issued in order and dealt round-robin to the XCDs)
+    std::stable_sort(items.begin(), items.end(), [](const psht::AdjItem &u, const psht::AdjItem &v) {
+        return (int64_t)(u.lb - u.la) * std::max(u.R, 1) > (int64_t)(v.lb - v.la) * std::max(v.R, 1);
+    });
+    p.adj_waves = G;
+    p.adj_rmax = rmax;
+    p.adj_seg = S;
+    p.n_adj_states = off;
+    p.alm_tail = (int64_t)(M + 1) * (2 * lmax + 1 - (M + 1)) / 2 + (M + 1);  // index(l = M + 1, m = M + 1)
+    if (!dalloc(p, p.d_adj_mu, (size_t)std::max<int64_t>(off, 1) * 4) ||
+        !dalloc(p, p.d_adj_k, (size_t)std::max<int64_t>(off, 1) * 2)) {
+        err = {PSHT_ERR_NOMEM, "allocating the adjoint recurrence states"};
+        return false;
+    }
+    psht::StateItem *d_sitems = nullptr;
+    if (!upload(p, p.d_adj_items, items, st) || !upload(p, d_sitems, sitems, st)) {
+        err = {PSHT_ERR_NOMEM, "uploading the adjoint work list"};
+        return false;
+    }
+    p.n_adj_items = (int)items.size();
+    hipError_t e = psht::launch_leg_adj_states(p, d_sitems, (int)sitems.size(), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        err = {PSHT_ERR_DEVICE, std::string("adjoint recurrence states: ") + hipGetErrorString(e)};
+        return false;
+    }
+    return true;
+}
 
 psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
                              const double *phi, double epsilon, int precision, hipStream_t st) {
@@ -210,7 +312,7 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         auto build_items = [&](int chunk, std::vector<psht::LegItem> &items) {
             const int group = (g.nring + chunk - 1) / chunk;
             const int ngroups = ((g.mmax + 1) + 7) / 8 * 8;
-            items.assign((size_t)ngroups * group, psht::LegItem{0, 0, 0, 0});
+            items.assign((size_t)ngroups * group, psht::LegItem{0, 0, 0});
             for (int m = 0; m <= g.mmax; ++m) {
                 int first = -1, last = -1;
                 for (int j = 0; j < g.nring; ++j)
@@ -281,62 +383,15 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         p.n_leg_items = (int)items.size();
         p.leg_rings_per_item = chunk;
         if (!upload(p, p.d_leg_items, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
-        // The adjoint runs one body for every item: the plain order (m ascending) is
-        // longest first.  Three rings per lane take about 30 % fewer wave-steps than
-        // two but hold 168 registers (three waves per SIMD instead of four); they pay
-        // off when the items fill the GPU at least twice over (lmax 4096: adjoint
-        // 3.2 -> 2.6 ms in the FP32 form, 3.3 -> 3.1 ms in FP64), while with about
-        // one round of items (lmax 2048) the longest items set the time and three
-        // rings per lane were 28 % slower.
-        int ra = psht::leg_adj_rings_per_lane();
-        if (ra == 0) {
-            build_items(64 * 3, items);
-            ra = (ncu > 0 && nonempty(items) >= (size_t)2 * ncu * 4 * 3) ? 3 : 2;
-        }
-        const int chunk_adj = 64 * ra;
-        p.leg_rings_per_item_adj = chunk_adj;
-        build_items(chunk_adj, items);
-        // Small plans leave most of the GPU idle in the adjoint (a few hundred
-        // items for thousands of wave slots), and its time is that of the
-        // longest items.  There each (m, ring chunk) is cut into S l-segments,
-        // consecutive in the list: segment k outputs l in [l0 + a_k, l0 + a_{k+1})
-        // and runs the recurrence alone below l0 + a_k, about 0.3 of a full step.
-        // With that price the offsets a_k = C (1 - 0.7^k) / 0.3 give every
-        // segment the same cost C.
-        p.leg_adj_lsegs = 1;
-        if (ra == 2 && psht::leg_adj_rings_per_lane() == 0 && ncu > 0) {
-            const double rounds = (double)nonempty(items) / ((double)ncu * 4 * 4);
-            const int nseg = rounds > 0 ? std::min(8, (int)(0.6 / rounds)) : 1;
-            if (nseg > 1) {
-                std::vector<psht::LegItem> seg(items.size() * nseg, psht::LegItem{0, 0, 0, 0});
-                for (size_t q = 0; q < items.size(); ++q) {
-                    const psht::LegItem &it = items[q];
-                    const int l0 = std::max(it.m, spin), L = lmax + 1 - l0;
-                    if (it.je <= it.jb || L < 8 * nseg) {  // short: one segment, the others empty
-                        seg[q * nseg] = it;
-                        for (int k = 1; k < nseg; ++k) seg[q * nseg + k] = psht::LegItem{it.m, 0, 0, 0};
-                        continue;
-                    }
-                    const double C = 0.3 * L / (1.0 - std::pow(0.7, nseg));
-                    int lo = l0;
-                    for (int k = 0; k < nseg; ++k) {
-                        const int hi = k + 1 == nseg ? lmax + 1
-                                                     : l0 + (int)std::lround(C * (1.0 - std::pow(0.7, k + 1)) / 0.3);
-                        psht::LegItem s2 = it;
-                        s2.lseg = lo | ((k + 1 == nseg ? 0 : hi) << 16);
-                        seg[q * nseg + k] = s2;
-                        lo = hi;
-                    }
-                }
-                items.swap(seg);
-                p.leg_adj_lsegs = nseg;
-            }
-        }
-        p.n_leg_items_adj = (int)items.size();
-        if (!upload(p, p.d_leg_items_adj, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
         build_items(64, items);
         p.n_leg_items64 = (int)items.size();
         if (!upload(p, p.d_leg_items64, items, st)) return fail(PSHT_ERR_NOMEM, "uploading Legendre work list");
+
+        // Segmented adjoint (k_leg_adj_seg): items (m, l-segment), each with every
+        // active ring of m in G waves of up to 6 rings per lane, started from
+        // recurrence states stored here for every ring and segment start.
+        psht::Error e2;
+        if (!build_adjoint_segments(p, ncu, st, e2)) return fail(e2);
     }
 
     // NUFFT tables
@@ -360,7 +415,10 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     p.ntx = (g.rows_used + p.tile_x - 1) / p.tile_x;
     p.nty = (g.Nphi + p.tile_y - 1) / p.tile_y;
     p.ntiles = p.ntx * p.nty;
-    if (!dalloc(p, p.d_tile_start, (size_t)p.ntiles + 1)) return fail(PSHT_ERR_NOMEM, "allocating sorted points");
+    if (!dalloc(p, p.d_tile_start, (size_t)p.ntiles + 1) || !dalloc(p, p.d_dropped, 2))
+        return fail(PSHT_ERR_NOMEM, "allocating sorted points");
+    if (psht::launch_fill_zero(p.d_dropped, 2 * sizeof(unsigned long long), st) != hipSuccess)
+        return fail(PSHT_ERR_DEVICE, "clearing the point counters");
     {
         ScopedDevFree keys, cursor, pstart, tpx, tpy, tperm;
         const size_t nn = (size_t)std::max<int64_t>(npoints, 1);
@@ -384,11 +442,18 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
         const size_t ne = (size_t)std::max<int64_t>(p.n_entries, 1);
         if (!dalloc(p, p.d_px, ne) || !dalloc(p, p.d_py, ne) || !dalloc(p, p.d_perm, ne))
             return fail(PSHT_ERR_NOMEM, "allocating sorted points");
+        // p.d_dropped[1] counts sorted entries outside their tile
         e = psht::launch_point_sort_order(p, static_cast<int32_t *>(keys.p), static_cast<const int32_t *>(pstart.p),
                                           static_cast<const double *>(tpx.p), static_cast<const double *>(tpy.p),
-                                          static_cast<const int32_t *>(tperm.p), st);
+                                          static_cast<const int32_t *>(tperm.p), p.d_dropped + 1, st);
+        unsigned long long bad = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bad, p.d_dropped + 1, sizeof(bad), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return device_fail(e, "point sort");
+        if (bad != 0)
+            return fail(PSHT_ERR_DEVICE, "internal error: " + std::to_string(bad) +
+                                             " sorted points have a stencil outside their NUFFT tile");
     }
 
     // workspace per map
@@ -522,7 +587,7 @@ psht_status adjoint_impl(psht_plan plan, int nmaps, const void *map, void *alm, 
         if (e == hipSuccess) e = timed(P, PSHT_T_SPREAD, st, [&] { return psht::launch_spread(P, m, U, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_PHI_ADJ, st, [&] { return psht::launch_phi_adjoint(P, U, V, st); });
         if (e == hipSuccess) e = timed(P, PSHT_T_THETA_ADJ, st, [&] { return psht::launch_theta_adjoint(P, V, F, st); });
-        if (e == hipSuccess) e = timed(P, PSHT_T_ALM_ZERO, st, [&] { return psht::launch_fill_zero(a, alm_bytes, st); });
+
         if (e == hipSuccess) e = timed(P, PSHT_T_LEG_ADJ, st, [&] { return psht::launch_leg_adjoint(P, F, a, mscale, st); });
         if (e != hipSuccess) return device_fail(e, "adjoint launch");
     }
@@ -599,6 +664,19 @@ psht_status psht_plan_timing(psht_plan plan, double *ms, int64_t *launches) {
 }
 
 const char *psht_last_error(void) { return g_last_error.c_str(); }
+
+psht_status psht_plan_check(psht_plan plan, int64_t *dropped, void *hip_stream) {
+    if (!plan || !dropped) return fail(PSHT_ERR_ARG, "plan or dropped is NULL");
+    *dropped = 0;
+    if (!plan->d_dropped) return PSHT_OK;
+    unsigned long long v = 0;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipMemcpyAsync(&v, plan->d_dropped, sizeof(v), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "reading the point counter");
+    *dropped = (int64_t)v;
+    return PSHT_OK;
+}
 
 psht_status psht_plan_geometry(int lmax, int spin, double theta_star, double epsilon, int precision,
                                psht_plan_info *info, double *ring_theta, double *ring_weight, int32_t *ring_mmax,

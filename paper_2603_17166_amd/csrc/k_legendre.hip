@@ -437,50 +437,6 @@ __device__ inline void adj_fold(int u, double c0, double c1, double c2, double c
     }
 }
 
-// CH steps from b of a staged chunk, all advancing: partial sums of the
-// lane's rings folded into w; independent work first (step coefficients,
-// partial sums), the dependent recurrence updates last.
-template <int R, bool SPIN, int CH>
-__device__ inline void adj_block(LegState<R, SPIN> &S, const double4 *sT, int b, const double *fpr,
-                                 const double *fpi, const double *fmr, const double *fmi, double *w,
-                                 double (*red)[CH][17], int row, int col) {
-    // coefficients one step ahead, not the whole block's at once (registers)
-    double3 tn = make_double3(sT[b].x, sT[b].y, sT[b].z);
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-        const double3 tc = tn;
-        if (u + 1 < CH) tn = make_double3(sT[b + u + 1].x, sT[b + u + 1].y, sT[b + u + 1].z);
-        __builtin_amdgcn_sched_barrier(0);
-        double cpl[R], cmi[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cpl[r] = fma(tc.x, S.y[r], tc.y);
-            if (SPIN) cmi[r] = fma(tc.x, S.y[r], tc.z);
-        }
-        double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
-            pa_r = fma(vp, fpr[r], pa_r);
-            pa_i = fma(vp, fpi[r], pa_i);
-            pb_r = fma(vm, fmr[r], pb_r);
-            pb_i = fma(vm, fmi[r], pb_i);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double np = fma(cpl[r], S.up[r], -S.upp[r]);
-            S.upp[r] = S.up[r];
-            S.up[r] = np;
-            if (SPIN) {
-                const double nm = fma(cmi[r], S.um[r], -S.ump[r]);
-                S.ump[r] = S.um[r];
-                S.um[r] = nm;
-            }
-        }
-        adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w, red, row, col);
-    }
-}
-
 // Scaled values in the adjoint.  A ring's map values enter its partial sums
 // only while its scale k is 0: they are held at zero while k < 0 and loaded
 // when k reaches 0, so the stored (scaled) values need no mask.
@@ -540,132 +496,294 @@ __device__ inline double quad_xor2(double x) {
     return __hiloint2double(hi, lo);
 }
 
-// CH = 8 values of l per transposed reduction.
-template <int R, bool SPIN, int CH, bool SEG>
-__global__ __launch_bounds__(64) void k_leg_adjoint(LegArgs a) {
-    static_assert(CH == 8, "the output stage maps 8 steps x 2 components x 4 lanes onto the wave");
-    constexpr int kAdjChunk = CH;
-    __shared__ double4 sbuf[2][kStage];
-    __shared__ double red[4][CH][17];
-    const int idx = leg_item_index(blockIdx.x, a.group);
-    if (idx >= a.nitems) return;
-    const LegItem it = a.items[idx];
-    if (it.je <= it.jb) return;
-    const int m = it.m, s = a.spin, lane = threadIdx.x;
-    const int l0 = m > s ? m : s, lmax = a.lmax;
-    if (l0 > lmax) return;
-    // l-segment of the item (small plans): outputs for l in [lacc, lhi]; the
-    // steps below lacc only run the recurrence
-    // (a kernel of its own, SEG, so that the plain one keeps its registers)
-    const int lacc = SEG ? it.lseg & 0xFFFF : 0;
-    const int lhi = SEG && (it.lseg >> 16) > 0 ? (it.lseg >> 16) - 1 : lmax;
+// ------------------------------------------------------- segmented adjoint
+//
+// Beyond its FMAs, the adjoint pays for reducing every l-step's four partial
+// sums over the 64 lanes (adj_fold and the LDS output stage): about 13
+// instructions per step and wave, whatever the number of rings a lane holds.
+// More rings per lane amortise that, but an order's rings then make few long
+// items (one or two per order), and the longest items set the time.  Items
+// cut in l restore the balance without repeating any recurrence: the item
+// (m, [la, lb)) starts from the recurrence state at l = la that the plan
+// stored for every ring and segment start (k_leg_adj_states).  The waves of a
+// workgroup hold disjoint rings of the order, fold their partial sums into
+// LDS, and wave 0 completes them over the waves and writes each output once
+// with a plain store (no atomics, no prior clear of the output).
 
+constexpr int kAdjMaxWaves = 4;
+constexpr int kAdjRedDoubles = 4 * 8 * 17;  // one wave's fold area per 8-step block
+
+struct AdjArgs {
+    LegArgs a;
+    const AdjItem *items;
+    int nitems;
+    const double4 *st_mu;
+    const int2 *st_k;
+};
+
+// Rings [j0 + 64 r + lane] of order m: seeds (first segment) or the stored states.
+template <int R, bool SPIN>
+__device__ inline void adj_seg_init(const AdjArgs &A, const AdjItem &it, int j0, int lane, LegState<R, SPIN> &S) {
+    const LegArgs &a = A.a;
+    if (it.soff < 0) {
+        const LegItem li{it.m, j0, it.je};
+        leg_init<R, SPIN>(a, li, lane, S);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r * 64 + lane;
+        S.act[r] = (j < it.je) && (a.ring_mmax[j] >= it.m);
+        S.y[r] = 0.0;
+        S.up[r] = S.upp[r] = S.um[r] = S.ump[r] = 0.0;
+        S.kp[r] = S.km[r] = 0;
+        if (S.act[r]) {
+            const int64_t q = it.soff + (j - it.jb);
+            const double4 v = A.st_mu[q];
+            const int2 k = A.st_k[q];
+            S.y[r] = a.ring_y[j];
+            S.up[r] = v.x;
+            S.upp[r] = v.y;
+            S.kp[r] = k.x;
+            if (SPIN) {
+                S.um[r] = v.z;
+                S.ump[r] = v.w;
+                S.km[r] = k.y;
+            } else {
+                S.um[r] = v.x;
+                S.km[r] = k.x;
+            }
+        }
+    }
+}
+
+// Zero outputs of order m for l in [l_from, l_to) (wave 0's lanes).
+__device__ inline void adj_zero_range(const LegArgs &a, int64_t base, int l_from, int l_to, int lane) {
+    for (int l = l_from + lane; l < l_to; l += 64) {
+        const int64_t kk = base + l;
+        reinterpret_cast<double2 *>(a.alm_out)[kk] = make_double2(0.0, 0.0);
+        reinterpret_cast<double2 *>(a.alm_out)[a.nalm + kk] = make_double2(0.0, 0.0);
+    }
+}
+
+// Eight steps from b of a staged chunk, all advancing (steps past the item's
+// last degree compute with zero-padded table entries; their folded values are
+// never written out): per ring, the step coefficients, the partial sums and
+// the recurrence update, folded step by step (adj_fold).
+template <int R, bool SPIN>
+__device__ inline void adj_seg_block(LegState<R, SPIN> &S, const double4 *sT, int b, const double *fpr,
+                                     const double *fpi, const double *fmr, const double *fmi, double (*red)[8][17],
+                                     int row, int col) {
+    double w[2];
+    double3 tn = make_double3(sT[b].x, sT[b].y, sT[b].z);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double3 tc = tn;
+        if (u + 1 < 8) tn = make_double3(sT[b + u + 1].x, sT[b + u + 1].y, sT[b + u + 1].z);
+        double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
+            pa_r = fma(vp, fpr[r], pa_r);
+            pa_i = fma(vp, fpi[r], pa_i);
+            pb_r = fma(vm, fmr[r], pb_r);
+            pb_i = fma(vm, fmi[r], pb_i);
+            const double np = fma(fma(tc.x, S.y[r], tc.y), vp, -S.upp[r]);
+            S.upp[r] = vp;
+            S.up[r] = np;
+            if (SPIN) {
+                const double nm = fma(fma(tc.x, S.y[r], tc.z), vm, -S.ump[r]);
+                S.ump[r] = vm;
+                S.um[r] = nm;
+            }
+        }
+        adj_fold<8>(u, pa_r, pa_i, pb_r, pb_i, w, red, row, col);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Workgroup barrier for LDS data only: waits for this wave's LDS operations,
+// not for its outstanding global loads (the next table chunk stays in flight
+// across the barrier), then s_barrier.
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited for
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int R, bool SPIN>
+__device__ void adj_seg_item(const AdjArgs &A, const AdjItem &it, int G, double4 (*sbuf)[kStage], double *redbase) {
+    const LegArgs &a = A.a;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = it.m, s = a.spin, lmax = a.lmax;
+    const int l0 = m > s ? m : s;
+    const int la = it.la, lhi = it.lb - 1;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double4 *T4 = a.coef + base;
-    if (lane < 32) sbuf[0][lane] = stage_entry(T4, l0, lmax, lane);
+    if (threadIdx.x < 32) sbuf[0][threadIdx.x] = stage_entry(T4, la, lmax, threadIdx.x);
+    if (wave == 0 && it.soff < 0) adj_zero_range(a, base, m, l0, lane);  // l < s: no such harmonic
 
+    const int j0 = it.jb + wave * 64 * R;
     LegState<R, SPIN> S;
-    leg_init<R, SPIN>(a, it, lane, S);
+    adj_seg_init<R, SPIN>(A, it, j0, lane, S);
     double fpr[R], fpi[R], fmr[R], fmi[R];
     const double2 *Fp = reinterpret_cast<const double2 *>(a.F) + (int64_t)(a.mmax + m) * a.nring;
     const double2 *Fm = reinterpret_cast<const double2 *>(a.F) + (int64_t)(a.mmax - m) * a.nring;
-    adj_load_f<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
+    adj_load_f<R, SPIN>(S, Fp, Fm, j0, lane, fpr, fpi, fmr, fmi);
     const double sgn_s = (s & 1) ? -1.0 : 1.0;
     const int row = lane >> 4, col = lane & 15;
     bool scaled = leg_any_scaled<R, SPIN>(S);
     __syncthreads();
 
-    int slot = 0;
-    for (int c = l0; c <= lhi; c += kStage) {
+    int slot = 0, buf = 0;
+    for (int c = la; c <= lhi; c += kStage) {
         const bool has_next = c + kStage <= lhi;
         double4 nv;
-        if (has_next && lane < 32) nv = stage_entry(T4, c + kStage, lmax, lane);
+        if (has_next && threadIdx.x < 32) nv = stage_entry(T4, c + kStage, lmax, threadIdx.x);
         const double4 *sT = sbuf[slot];
         const int n = min(kStage, lhi + 1 - c);
-        for (int b = 0; b < n; b += kAdjChunk) {
-            // per-lane partial sums over the lane's rings, 4 components per l,
-            // folded step by step (adj_fold)
-            double w[2];
-            const bool full = c + b + kAdjChunk <= lhi;  // every step of the block exists and advances
-            if ((SEG && c + b + kAdjChunk <= lacc) || (scaled && !leg_live<R, SPIN>(S))) {
-                // below the item's l-segment, or every active lane below the
-                // double range (all partial sums vanish): the block needs
-                // neither sums nor reduction
-                if (full) advance_steps<R, SPIN, true, kAdjChunk>(S, sT, b, n, c, lhi);
-                else advance_steps<R, SPIN, false, kAdjChunk>(S, sT, b, min(b + kAdjChunk, n), c, lhi);
-                if (!SEG || scaled) {  // without segments the branch is only taken while scaled
-                    adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
-                    scaled = leg_any_scaled<R, SPIN>(S);
-                }
-                continue;
-            }
-            if (full) {
-                adj_block<R, SPIN, CH>(S, sT, b, fpr, fpi, fmr, fmi, w, red, row, col);
-            } else
+        for (int b = 0; b < n; b += 8) {
+            double(*red)[8][17] = reinterpret_cast<double(*)[8][17]>(redbase + (buf * G + wave) * kAdjRedDoubles);
+            if (scaled && !leg_live<R, SPIN>(S)) {
+                // every active ring of this wave is below the double range: its
+                // partial sums are zero, only the recurrence runs
+                advance_steps<R, SPIN, true, 8>(S, sT, b, n, c, lhi);
 #pragma unroll
-            for (int u = 0; u < kAdjChunk; ++u) {
-                const int t = b + u;
-                double pa_r = 0.0, pa_i = 0.0, pb_r = 0.0, pb_i = 0.0;
-                if (t < n) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const double vp = S.up[r], vm = SPIN ? S.um[r] : S.up[r];
-                        pa_r = fma(vp, fpr[r], pa_r);
-                        pa_i = fma(vp, fpi[r], pa_i);
-                        pb_r = fma(vm, fmr[r], pb_r);
-                        pb_i = fma(vm, fmi[r], pb_i);
-                    }
-                    if (c + t < lhi) leg_advance<R, SPIN>(S, sT[t]);
-                }
-                adj_fold<CH>(u, pa_r, pa_i, pb_r, pb_i, w, red, row, col);
+                for (int k = 0; k < 8; ++k) red[row][k][col] = 0.0;
+            } else {
+                adj_seg_block<R, SPIN>(S, sT, b, fpr, fpi, fmr, fmi, red, row, col);
             }
             if (scaled) {
-                adj_renorm<R, SPIN>(S, Fp, Fm, it.jb, lane, fpr, fpi, fmr, fmi);
+                adj_renorm<R, SPIN>(S, Fp, Fm, j0, lane, fpr, fpi, fmr, fmi);
                 scaled = leg_any_scaled<R, SPIN>(S);
             }
-            // The remaining sums over the 16 lanes of each row go through LDS.
-            // Step u, component c sits in row 2 (c >> 1) + (u & 1), value
-            // 2 (u >> 1) + (c & 1): A_x (c = x) and B_x (c = 2 + x) share the
-            // value index, two rows apart.  Lane (u = lane >> 3, x = bit 2,
-            // h = lane & 3) adds columns 4h .. 4h + 3 of both, the quad of lanes
-            // h = 0..3 completes the sums, and lanes h = 0 and 1 form the g~ and
-            // c~ outputs of component x.
-            __syncthreads();
-            const int u = lane >> 3, x = (lane >> 2) & 1, h = lane & 3;
-            const int qa = u & 1, kv = 2 * (u >> 1) + x;
-            double sa = 0.0, sb = 0.0;
+            // The fold areas of this block are double buffered: the next block
+            // writes the other one, so one barrier per block suffices.
+            lds_barrier();
+            if (wave == 0) {
+                // Step u, component c of wave g sits in row 2 (c >> 1) + (u & 1),
+                // value 2 (u >> 1) + (c & 1) of the wave's fold area.  Lane
+                // (u = lane >> 3, x = bit 2, h = lane & 3) adds columns 4h .. 4h + 3
+                // of A_x and B_x over the waves, the lane quad completes the sums,
+                // and lanes h = 0 and 1 write g~ and c~ of component x.
+                const int u = lane >> 3, x = (lane >> 2) & 1, h = lane & 3;
+                const int qa = u & 1, kv = 2 * (u >> 1) + x;
+                double sa = 0.0, sb = 0.0;
+                for (int g = 0; g < G; ++g) {
+                    const double(*rg)[8][17] =
+                        reinterpret_cast<const double(*)[8][17]>(redbase + (buf * G + g) * kAdjRedDoubles);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                sa += red[qa][kv][4 * h + j];
-                sb += red[qa + 2][kv][4 * h + j];
-            }
-            sa += quad_xor1(sa);
-            sb += quad_xor1(sb);
-            sa += quad_xor2(sa);
-            sb += quad_xor2(sb);
-            const int t = b + u;
-            // Im g~_l0 and Im c~_l0 vanish exactly for m = 0 (reality condition).
-            const bool imag = h == 0 ? x == 1 : x == 0;
-            if (h < 2 && t < n && c + t >= lacc && !(m == 0 && imag)) {
-                const int64_t kk = base + c + t;
-                const double hP = (m == 0 ? 0.5 : 0.5 * a.mscale) * sT[t].w;
-                double val;
-                double *dst;
-                if (h == 0) {  // g~: -hP (A + (-1)^s B), component x
-                    val = -hP * (sa + sgn_s * sb);
-                    dst = a.alm_out + 2 * kk + x;
-                } else {  // c~ = (i/2) P (A - (-1)^s B): Im from the real parts, Re from the imaginary ones
-                    const double d = hP * (sa - sgn_s * sb);
-                    val = x == 0 ? d : -d;
-                    dst = a.alm_out + 2 * (a.nalm + kk) + (1 - x);
+                    for (int j = 0; j < 4; ++j) {
+                        sa += rg[qa][kv][4 * h + j];
+                        sb += rg[qa + 2][kv][4 * h + j];
+                    }
                 }
-                atomicAdd(dst, val);
+                sa += quad_xor1(sa);
+                sb += quad_xor1(sb);
+                sa += quad_xor2(sa);
+                sb += quad_xor2(sb);
+                const int t = b + u;
+                if (h < 2 && t < n) {
+                    const int64_t kk = base + c + t;
+                    const double hP = (m == 0 ? 0.5 : 0.5 * a.mscale) * sT[t].w;
+                    // Im g~_l0 and Im c~_l0 vanish (reality condition)
+                    const bool imag = h == 0 ? x == 1 : x == 0;
+                    double val;
+                    double *dst;
+                    if (h == 0) {  // g~ = -hP (A + (-1)^s B), component x
+                        val = -hP * (sa + sgn_s * sb);
+                        dst = a.alm_out + 2 * kk + x;
+                    } else {  // c~ = (i/2) P (A - (-1)^s B): Im from the real parts, Re from the imaginary ones
+                        const double d = hP * (sa - sgn_s * sb);
+                        val = x == 0 ? d : -d;
+                        dst = a.alm_out + 2 * (a.nalm + kk) + (1 - x);
+                    }
+                    *dst = (m == 0 && imag) ? 0.0 : val;
+                }
             }
-            __syncthreads();
+            buf ^= 1;
         }
-        if (has_next && lane < 32) sbuf[slot ^ 1][lane] = nv;
-        __syncthreads();
+        if (has_next && threadIdx.x < 32) sbuf[slot ^ 1][threadIdx.x] = nv;
+        lds_barrier();
         slot ^= 1;
+    }
+}
+
+// One workgroup of G = blockDim.x / 64 waves per item (G = 1, 2 or 4, so that
+// whole workgroups fill a CU's wave slots); rings per lane chosen per item
+// (the waves of an item share it) up to RMAX.  About 34 VGPRs per ring: the
+// RMAX = 6 kernel takes 245 (two waves per SIMD), the RMAX = 4 kernel is
+// held to three waves per SIMD.
+template <bool SPIN, int RMAX>
+__device__ inline void adj_seg_dispatch(const AdjArgs &A) {
+    __shared__ double4 sbuf[2][kStage];
+    extern __shared__ double redbase[];  // fold areas [2][G][4][8][17]
+    if ((int)blockIdx.x >= A.nitems) return;
+    const AdjItem it = A.items[blockIdx.x];
+    const int G = blockDim.x >> 6;
+    switch (it.R) {
+        case 0:
+            // no active ring: the order's outputs are zero
+            if (threadIdx.x < 64)
+                adj_zero_range(A.a, (int64_t)it.m * (2 * A.a.lmax + 1 - it.m) / 2, it.la, it.lb, threadIdx.x);
+            break;
+        case 1: adj_seg_item<1, SPIN>(A, it, G, sbuf, redbase); break;
+        case 2: adj_seg_item<2, SPIN>(A, it, G, sbuf, redbase); break;
+        case 3: adj_seg_item<3, SPIN>(A, it, G, sbuf, redbase); break;
+        case 4: adj_seg_item<4, SPIN>(A, it, G, sbuf, redbase); break;
+        case 5: if constexpr (RMAX >= 5) adj_seg_item<5, SPIN>(A, it, G, sbuf, redbase); break;
+        default: if constexpr (RMAX >= 6) adj_seg_item<6, SPIN>(A, it, G, sbuf, redbase); break;
+    }
+}
+
+template <bool SPIN>
+__global__ __launch_bounds__(256, 2) void k_leg_adj_seg6(AdjArgs A) { adj_seg_dispatch<SPIN, 6>(A); }
+template <bool SPIN>
+__global__ __launch_bounds__(256, 3) void k_leg_adj_seg4(AdjArgs A) { adj_seg_dispatch<SPIN, 4>(A); }
+
+// Plan time: one lane per ring runs the recurrence of order m from its seed
+// and stores (mu_l, mu_{l-1}) and the scales at every segment start
+// l = l0 + k S, k >= 1.
+template <bool SPIN>
+__global__ __launch_bounds__(64) void k_leg_adj_states(LegArgs a, const StateItem *items, int nitems, double4 *st_mu,
+                                                       int2 *st_k) {
+    if ((int)blockIdx.x >= nitems) return;
+    const StateItem it = items[blockIdx.x];
+    const int j = it.j0 + (int)threadIdx.x;
+    if (j >= it.je) return;
+    const int m = it.m, s = a.spin, lmax = a.lmax;
+    const int l0 = m > s ? m : s;
+    const double y = a.ring_y[j];
+    double up, um, upp = 0.0, ump = 0.0;
+    int kp, km;
+    leg_seed(a.kmant[m], a.kexp[m], m, s, a.ring_ch[j], a.ring_sh[j], up, kp, um, km);
+    if (!SPIN) {
+        um = up;
+        km = kp;
+    }
+    const double4 *T4 = a.coef + (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const int64_t nr = it.je - it.jb;
+    const int lend = l0 + (it.nseg - 1) * it.S;
+    int k = 1;
+    for (int l = l0; l < lend && l < lmax; ++l) {
+        const double4 t = T4[l];
+        const double np = fma(fma(t.x, y, t.y), up, -upp);
+        upp = up;
+        up = np;
+        leg_rescale(up, upp, kp);
+        if (SPIN) {
+            const double nm = fma(fma(t.x, y, t.z), um, -ump);
+            ump = um;
+            um = nm;
+            leg_rescale(um, ump, km);
+        }
+        if (l + 1 == l0 + k * it.S) {
+            const int64_t q = it.soff + (int64_t)(k - 1) * nr + (j - it.jb);
+            st_mu[q] = SPIN ? make_double4(up, upp, um, ump) : make_double4(up, upp, up, upp);
+            st_k[q] = make_int2(kp, SPIN ? km : kp);
+            ++k;
+        }
     }
 }
 
@@ -858,16 +976,11 @@ static int rings_knob(const char *name, int dflt) {
     return (v >= 1 && v <= 4) || v == 8 ? v : dflt;
 }
 
-// Rings per lane: PSHT_LEG_R (synthesis) and PSHT_LEG_RA (adjoint), each 1,
-// 2, 3, 4 or 8, fix them for tuning runs; without them 0, and the plan
-// chooses by the size of its work list (synthesis 1 or 2, adjoint 2 or 3).
+// Rings per lane of the synthesis: PSHT_LEG_R (1, 2, 3, 4 or 8) fixes it for
+// tuning runs; without it 0, and the plan chooses 1 or 2 by the size of its
+// work list.
 int leg_rings_per_lane() {
     static const int r = rings_knob("PSHT_LEG_R", 0);
-    return r;
-}
-
-int leg_adj_rings_per_lane() {
-    static const int r = rings_knob("PSHT_LEG_RA", 0);
     return r;
 }
 
@@ -878,23 +991,6 @@ static void leg_synth_r(const psht_plan_s &p, const void *alm, double *F, double
     dim3 grid(p.n_leg_items), block(64);
     if (p.g.spin) hipLaunchKernelGGL((k_leg_synth<R, true>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_leg_synth<R, false>), grid, block, 0, st, a);
-}
-
-template <int R>
-static void leg_adjoint_r(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
-    LegArgs a = leg_args<R>(p, nullptr, alm, const_cast<double *>(F));
-    a.items = p.d_leg_items_adj;
-    a.nitems = p.n_leg_items_adj;
-    a.group *= p.leg_adj_lsegs;  // the l-segments of a (m, ring chunk) are consecutive items
-    a.mscale = mscale;
-    dim3 grid(p.n_leg_items_adj), block(64);
-    if (R == 2 && p.leg_adj_lsegs > 1) {
-        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8, true>), grid, block, 0, st, a);
-    } else {
-        if (p.g.spin) hipLaunchKernelGGL((k_leg_adjoint<R, true, 8, false>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_leg_adjoint<R, false, 8, false>), grid, block, 0, st, a);
-    }
 }
 
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st) {
@@ -929,16 +1025,48 @@ hipError_t launch_leg_synth_batch(const psht_plan_s &p, int nb, const void *alm0
     return hipGetLastError();
 }
 
-hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
-    if (p.n_leg_items_adj == 0) return hipSuccess;
-    switch (p.leg_rings_per_item_adj / 64) {
-        case 1: leg_adjoint_r<1>(p, F, alm, mscale, st); break;
-        case 3: leg_adjoint_r<3>(p, F, alm, mscale, st); break;
-        case 2: leg_adjoint_r<2>(p, F, alm, mscale, st); break;
-        case 8: leg_adjoint_r<8>(p, F, alm, mscale, st); break;
-        default: leg_adjoint_r<4>(p, F, alm, mscale, st); break;
+hipError_t launch_leg_adj_states(const psht_plan_s &p, const StateItem *items, int nitems, hipStream_t st) {
+    if (nitems == 0) return hipSuccess;
+    LegArgs a = leg_args<1>(p, nullptr, nullptr, nullptr);
+    double4 *mu = reinterpret_cast<double4 *>(p.d_adj_mu);
+    int2 *k = reinterpret_cast<int2 *>(p.d_adj_k);
+    if (p.g.spin) hipLaunchKernelGGL(k_leg_adj_states<true>, dim3(nitems), dim3(64), 0, st, a, items, nitems, mu, k);
+    else hipLaunchKernelGGL(k_leg_adj_states<false>, dim3(nitems), dim3(64), 0, st, a, items, nitems, mu, k);
+    return hipGetLastError();
+}
+
+static hipError_t leg_adjoint_seg(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
+    // orders above mmax have no ring: their outputs (the tail of g and of c) are zero
+    const int64_t nalm = (int64_t)(p.g.lmax + 1) * (p.g.lmax + 2) / 2;
+    if (p.alm_tail < nalm) {
+        double2 *g = static_cast<double2 *>(alm);
+        hipError_t e = launch_fill_zero(g + p.alm_tail, (size_t)(nalm - p.alm_tail) * 16, st);
+        if (e == hipSuccess) e = launch_fill_zero(g + nalm + p.alm_tail, (size_t)(nalm - p.alm_tail) * 16, st);
+        if (e != hipSuccess) return e;
+    }
+    if (p.n_adj_items == 0) return hipSuccess;
+    AdjArgs A;
+    A.a = leg_args<1>(p, nullptr, alm, const_cast<double *>(F));
+    A.a.mscale = mscale;
+    A.items = p.d_adj_items;
+    A.nitems = p.n_adj_items;
+    A.st_mu = reinterpret_cast<const double4 *>(p.d_adj_mu);
+    A.st_k = reinterpret_cast<const int2 *>(p.d_adj_k);
+    const int G = p.adj_waves;
+    const size_t lds = sizeof(double) * 2 * G * kAdjRedDoubles;
+    const dim3 grid(p.n_adj_items), block(64 * G);
+    if (p.adj_rmax <= 4) {
+        if (p.g.spin) hipLaunchKernelGGL(k_leg_adj_seg4<true>, grid, block, lds, st, A);
+        else hipLaunchKernelGGL(k_leg_adj_seg4<false>, grid, block, lds, st, A);
+    } else {
+        if (p.g.spin) hipLaunchKernelGGL(k_leg_adj_seg6<true>, grid, block, lds, st, A);
+        else hipLaunchKernelGGL(k_leg_adj_seg6<false>, grid, block, lds, st, A);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
+    return leg_adjoint_seg(p, F, alm, mscale, st);
 }
 
 }  // namespace psht

@@ -18,6 +18,7 @@
 // LDS: interpolation reads it once from HBM; spreading accumulates into it
 // (in double) with LDS atomics and flushes it with one global atomic per
 // non-zero cell and component.
+#include "nufft_index.h"
 #include "psht_internal.h"
 
 namespace psht {
@@ -33,9 +34,11 @@ struct NufftArgs {
     const int32_t *perm;
     const int32_t *tile_start;
     const double *poly;  // kernel polynomial table of the inner taps
+    TileGeom geo;
+    // points whose stencil left their tile (never expected: the plan verifies
+    // the sort; counted, not silently skipped)
+    unsigned long long *dropped;
 };
-
-__device__ __host__ inline int stencil_origin(double X, int W) { return (int)ceil(X - 0.5 * W); }
 
 // Row stride (in elements) of a tile's subgrid in LDS: odd, so that the
 // stencil origins (li, lj) of the slots a wave handles in one instruction
@@ -173,12 +176,14 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
         if (pm < 0) continue;  // dummy entry of an odd cell
         const double X = a.px[p], Y = a.py[p];
         const int a0 = stencil_origin(X, W), b0 = stencil_origin(Y, W);
-        int b0m = b0 % a.Nphi;
-        if (b0m < 0) b0m += a.Nphi;
-        const int li = a0 - a.row_lo - r0, lj = b0m - c0;
-        // By construction of the sort 0 <= li < tile_x and 0 <= lj < tile_y; the
-        // guard only keeps LDS accesses in bounds.
-        if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
+        int li, lj;
+        tile_local(a.geo, X, Y, t, li, lj);
+        // The plan verified 0 <= li < tile_x, 0 <= lj < tile_y for every entry;
+        // the guard keeps LDS accesses in bounds and counts what it skips.
+        if (!in_tile(a.geo, li, lj)) {
+            atomicAdd(a.dropped, 1ull);
+            continue;
+        }
         double kw[2][W];
         {
             const double xs[2] = {X, Y};
@@ -232,10 +237,12 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         const int p = 2 * q;
         const double X = a.px[p], Y = a.py[p], X2 = a.px[p + 1], Y2 = a.py[p + 1];
         const int a0 = stencil_origin(X, W), b0 = stencil_origin(Y, W);
-        int b0m = b0 % a.Nphi;
-        if (b0m < 0) b0m += a.Nphi;
-        const int li = a0 - a.row_lo - r0, lj = b0m - c0;
-        if (li < 0 || li >= a.tile_x || lj < 0 || lj >= a.tile_y) continue;
+        int li, lj;
+        tile_local(a.geo, X, Y, t, li, lj);
+        if (!in_tile(a.geo, li, lj)) {
+            atomicAdd(a.dropped, (a.perm[p + 1] >= 0) ? 2ull : 1ull);
+            continue;
+        }
         double kw[4][W];
         {
             // the partner has the same cell, but its own unwrapped origin: across
@@ -292,6 +299,8 @@ static NufftArgs nufft_args(const psht_plan_s &p) {
     a.perm = p.d_perm;
     a.tile_start = p.d_tile_start;
     a.poly = p.d_es_poly;
+    a.geo = tile_geom(p);
+    a.dropped = p.d_dropped;
     return a;
 }
 
@@ -416,32 +425,7 @@ hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n,
     return hipGetLastError();
 }
 
-struct SortArgs {
-    double sx, sy;
-    int W, row_lo, rows_used, Nphi, tile_x, tile_y, ntx, nty;
-};
-
-// Grid coordinates of a point; phi is reduced to [0, 2 pi).
-__device__ inline void point_grid(const SortArgs &a, double theta, double phi, double &X, double &Y) {
-    const double twopi = 2.0 * M_PI;
-    double f = phi - twopi * floor(phi / twopi);
-    if (f >= twopi) f -= twopi;
-    if (f < 0.0) f = 0.0;
-    X = theta * a.sx;
-    Y = f * a.sy;
-    if (Y >= (double)a.Nphi) Y -= (double)a.Nphi;
-}
-
-__device__ inline int point_tile(const SortArgs &a, double X, double Y) {
-    const int a0 = stencil_origin(X, a.W), b0 = stencil_origin(Y, a.W);
-    int b0m = b0 % a.Nphi;
-    if (b0m < 0) b0m += a.Nphi;
-    int tx = (a0 - a.row_lo) / a.tile_x;
-    int ty = b0m / a.tile_y;
-    tx = min(max(tx, 0), a.ntx - 1);
-    ty = min(max(ty, 0), a.nty - 1);
-    return tx * a.nty + ty;
-}
+typedef TileGeom SortArgs;
 
 __global__ void k_point_keys(SortArgs a, const double *theta, const double *phi, int64_t n, int32_t *keys,
                              int32_t *count) {
@@ -504,13 +488,29 @@ __global__ void k_point_scatter(SortArgs a, const double *theta, const double *p
 // that consecutive lanes update in one instruction fall in distinct LDS banks.
 constexpr int kOrderThreads = 256;
 
-__device__ inline int cell_in_tile(const SortArgs &a, double X, double Y, int r0, int c0) {
-    const int a0 = stencil_origin(X, a.W), b0 = stencil_origin(Y, a.W);
-    int b0m = b0 % a.Nphi;
-    if (b0m < 0) b0m += a.Nphi;
-    const int li = min(max(a0 - a.row_lo - r0, 0), a.tile_x - 1);
-    const int lj = min(max(b0m - c0, 0), a.tile_y - 1);
+// Cell of a point inside tile t (clamped; k_tile_verify checks that no clamp
+// is ever needed).
+__device__ inline int cell_in_tile(const SortArgs &a, double X, double Y, int t) {
+    int li, lj;
+    tile_local(a, X, Y, t, li, lj);
+    li = min(max(li, 0), a.tile_x - 1);
+    lj = min(max(lj, 0), a.tile_y - 1);
     return li * a.tile_y + lj;
+}
+
+// Entries whose stencil origin lies outside their tile (plan-time check of the sort).
+__global__ void k_tile_verify(SortArgs a, const int32_t *tile_start, int ntiles, const double *px, const double *py,
+                              const int32_t *perm, unsigned long long *bad) {
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int p0 = tile_start[t], p1 = tile_start[t + 1];
+    unsigned long long nbad = 0;
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        int li, lj;
+        tile_local(a, px[p], py[p], t, li, lj);
+        if (perm[p] >= 0 && !in_tile(a, li, lj)) ++nbad;
+    }
+    if (nbad) atomicAdd(bad, nbad);
 }
 
 // Entries (2 per slot) of every tile: sum over cells of 2 ceil(count / 2).
@@ -527,12 +527,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_entries(SortArgs a, cons
         if (threadIdx.x == 0) entries[t] = 0;
         return;
     }
-    const int r0 = (t / a.nty) * a.tile_x, c0 = (t % a.nty) * a.tile_y;
     for (int c = threadIdx.x; c < C; c += kOrderThreads) cnt[c] = 0;
     if (threadIdx.x == 0) s_tot = 0;
     __syncthreads();
     for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads)
-        atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
+        atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], t)], 1);
     __syncthreads();
     int loc = 0;
     for (int c = threadIdx.x; c < C; c += kOrderThreads) loc += 2 * ((cnt[c] + 1) / 2);
@@ -556,12 +555,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const 
     const int p0 = pstart[t], p1 = pstart[t + 1];
     if (p0 == p1) return;
     const int e0 = estart[t];
-    const int r0 = (t / a.nty) * a.tile_x, c0 = (t % a.nty) * a.tile_y;
     const int stride = tile_row_stride(a.tile_y, a.W);
     for (int c = threadIdx.x; c < C; c += kOrderThreads) cnt[c] = 0;
     __syncthreads();
     for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads)
-        rank[p] = atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], r0, c0)], 1);
+        rank[p] = atomicAdd(&cnt[cell_in_tile(a, tpx[p], tpy[p], t)], 1);
     __syncthreads();
     // one thread per class walks its cells in row-major order
     if (threadIdx.x < kBankClasses) {
@@ -580,7 +578,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const 
     __syncthreads();
     for (int p = p0 + threadIdx.x; p < p1; p += kOrderThreads) {
         const int r = rank[p];
-        const int cell = cell_in_tile(a, tpx[p], tpy[p], r0, c0);
+        const int cell = cell_in_tile(a, tpx[p], tpy[p], t);
         const int li = cell / a.tile_y, lj = cell - li * a.tile_y;
         const int k = (li * stride + lj) % kBankClasses;
         const int R = first[cell] + r / 2;  // class rank of the point's slot
@@ -605,8 +603,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(SortArgs a, const 
 
 size_t tile_order_lds_bytes(int tile_x, int tile_y) { return sizeof(int32_t) * 2 * (size_t)tile_x * tile_y; }
 
-static SortArgs sort_args(const psht_plan_s &p) {
-    SortArgs a;
+TileGeom tile_geom(const psht_plan_s &p) {
+    TileGeom a;
     a.sx = p.g.sx;
     a.sy = p.g.sy;
     a.W = p.g.W;
@@ -623,7 +621,7 @@ static SortArgs sort_args(const psht_plan_s &p) {
 hipError_t launch_point_sort_count(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
                                    int32_t *d_cursor, int32_t *d_pstart, double *tpx, double *tpy, int32_t *tperm,
                                    hipStream_t st) {
-    const SortArgs a = sort_args(p);
+    const SortArgs a = tile_geom(p);
     const int64_t n = p.npts;
     hipError_t e = launch_fill_zero(d_cursor, sizeof(int32_t) * (size_t)p.ntiles, st);
     if (e != hipSuccess) return e;
@@ -647,13 +645,16 @@ hipError_t launch_point_sort_count(psht_plan_s &p, const double *theta, const do
 }
 
 hipError_t launch_point_sort_order(psht_plan_s &p, int32_t *d_keys, const int32_t *d_pstart, const double *tpx,
-                                   const double *tpy, const int32_t *tperm, hipStream_t st) {
+                                   const double *tpy, const int32_t *tperm, unsigned long long *d_bad,
+                                   hipStream_t st) {
     if (p.npts == 0) return hipSuccess;
-    const SortArgs a = sort_args(p);
+    const SortArgs a = tile_geom(p);
     // keys are no longer needed: they hold the per-point ranks from here on
     hipLaunchKernelGGL(k_tile_order, dim3((unsigned)p.ntiles), dim3(kOrderThreads),
                        tile_order_lds_bytes(p.tile_x, p.tile_y), st, a, d_pstart, p.d_tile_start, tpx, tpy, tperm,
                        d_keys, p.d_px, p.d_py, p.d_perm);
+    hipLaunchKernelGGL(k_tile_verify, dim3((unsigned)p.ntiles), dim3(256), 0, st, a, p.d_tile_start, p.ntiles, p.d_px,
+                       p.d_py, p.d_perm, d_bad);
     return hipGetLastError();
 }
 

@@ -92,10 +92,29 @@ std::shared_ptr<LegTable> leg_table_get(int lmax, int spin, Error &err);
 
 struct LegItem {
     int32_t m, jb, je;  // rings [jb, je) for this m
-    // adjoint items of small plans: the item's outputs are the l in
-    // [lseg & 0xFFFF, (lseg >> 16) - 1] (its recurrence runs from the seed up to
-    // there); lseg = 0 means every l
-    int32_t lseg;
+};
+
+// Work item of the segmented Legendre adjoint: one workgroup of `waves`
+// wavefronts computes the outputs l in [la, lb) of order m from every active
+// ring of m.  Wave w holds the 64 R consecutive rings from jb + 64 R w, R per
+// lane.  An item that does not start at the seed l0 = max(m, s) starts from the
+// recurrence state stored at plan time for l = la (index soff of the item's
+// first ring; -1 for the first segment).  R = 0: the order has no active ring
+// and its outputs are zero.
+struct AdjItem {
+    int32_t m, jb, je;
+    int32_t la, lb;
+    int32_t R;
+    int64_t soff;
+};
+
+// Plan-time recurrence states of the segmented adjoint: one lane per ring of
+// the 64 rings from j0 of order m (rings [jb, je) of the order), storing the
+// state at the nseg - 1 segment starts l0 + k S, k = 1..nseg-1, at
+// soff + (k - 1) (je - jb) + (j - jb).
+struct StateItem {
+    int32_t m, j0, jb, je, nseg, S;
+    int64_t soff;
 };
 
 // ------------------------------------------------------------------- plan
@@ -118,10 +137,16 @@ struct psht_plan_s {
     psht::LegItem *d_leg_items = nullptr;
     int n_leg_items = 0;
     int leg_rings_per_item = 0;
-    psht::LegItem *d_leg_items_adj = nullptr;  // adjoint list (its own rings per lane and order)
-    int n_leg_items_adj = 0;
-    int leg_rings_per_item_adj = 0;
-    int leg_adj_lsegs = 1;  // l-segments per (m, ring chunk) in the adjoint list
+    // segmented adjoint: items, waves per workgroup, segment length, stored states
+    psht::AdjItem *d_adj_items = nullptr;
+    int n_adj_items = 0;
+    int adj_waves = 1;
+    int adj_rmax = 6;  // largest rings per lane of any item (selects the kernel instantiation)
+    int adj_seg = 0;
+    double *d_adj_mu = nullptr;    // [state] {mu+_l, mu+_{l-1}, mu-_l, mu-_{l-1}}
+    int32_t *d_adj_k = nullptr;    // [state] {k+, k-}
+    int64_t n_adj_states = 0;
+    int64_t alm_tail = 0;          // first coefficient index of order mmax + 1 (outputs zero from there)
     psht::LegItem *d_leg_items64 = nullptr;  // 64-ring chunks (batched-maps kernel)
     int n_leg_items64 = 0;
     std::shared_ptr<psht::LegTable> leg;
@@ -136,6 +161,7 @@ struct psht_plan_s {
     int32_t *d_perm = nullptr;
     int32_t *d_tile_start = nullptr;  // ntiles + 1, in entries (2 per slot)
     int64_t n_entries = 0;            // slot entries of all tiles (points + dummies)
+    unsigned long long *d_dropped = nullptr;  // points the NUFFT kernels had to skip (expected 0)
     // workspace layout (bytes, per map)
     size_t ws_F = 0, ws_V = 0, ws_U = 0, ws_per_map = 0;
     size_t resident = 0;
@@ -155,6 +181,11 @@ namespace psht {
 // every order m >= 1; 1 for the plain transforms.
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st);
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st);
+constexpr int kAdjMaxWavesHost = 4;  // waves per workgroup of the segmented adjoint
+constexpr int kAdjMaxRings = 6;      // rings per lane of the segmented adjoint
+// Plan time: the recurrence states of the segmented adjoint.
+hipError_t launch_leg_adj_states(const psht_plan_s &p, const StateItem *items, int nitems, hipStream_t st);
+
 // Legendre synthesis of nb <= kMaxLegBatch maps in one pass (MFMA): map b reads
 // its coefficients at alm0 + b alm_stride and writes F at F0 + b ws_stride
 // (its own workspace).
@@ -189,13 +220,17 @@ hipError_t launch_point_stats(const double *theta, const double *phi, int64_t n,
 hipError_t launch_point_sort_count(psht_plan_s &p, const double *theta, const double *phi, int32_t *d_keys,
                                    int32_t *d_cursor, int32_t *d_pstart, double *tpx, double *tpy, int32_t *tperm,
                                    hipStream_t st);
+// It also counts into *d_bad the entries whose stencil origin lies outside their
+// tile (the plan fails if there are any).
 hipError_t launch_point_sort_order(psht_plan_s &p, int32_t *d_keys, const int32_t *d_pstart, const double *tpx,
-                                   const double *tpy, const int32_t *tperm, hipStream_t st);
+                                   const double *tpy, const int32_t *tperm, unsigned long long *d_bad,
+                                   hipStream_t st);
+struct TileGeom;
+TileGeom tile_geom(const psht_plan_s &p);
 
-// Rings per lane of the Legendre synthesis and adjoint kernels (a work item
-// covers 64 x this many rings); 0 leaves the choice to the plan.
+// Rings per lane of the Legendre synthesis kernel (a work item covers 64 x
+// this many rings); 0 leaves the choice to the plan.
 int leg_rings_per_lane();
-int leg_adj_rings_per_lane();
 
 // Largest FFT length one workgroup transforms in LDS.
 constexpr int kFftMaxLds64 = 8192;

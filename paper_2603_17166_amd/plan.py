@@ -155,6 +155,13 @@ class Plan:
                                                 ws.numel(), _stream(stream)))
         return out[0] if single else out
 
+    def dropped_points(self, stream=None) -> int:
+        """Points the NUFFT kernels skipped because their stencil left their tile (0 unless broken)."""
+        v = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().psht_plan_check(self._h, ctypes.byref(v), _stream(stream)))
+        return int(v.value)
+
     def set_timing(self, enable: bool = True, stages=None) -> None:
         """Record HIP events around the stage launches of later calls (every stage,
         or only those named in `stages`) and reset the totals."""
