@@ -396,7 +396,8 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
 
     // NUFFT tables
     if (!upload(p, p.d_psihat_t, g.psihat_theta, st) || !upload(p, p.d_psihat_p, g.psihat_phi, st) ||
-        (!g.es_poly.empty() && !upload(p, p.d_es_poly, g.es_poly, st)))
+        (!g.es_poly.empty() && !upload(p, p.d_es_poly, g.es_poly, st)) ||
+        (!g.es_poly32.empty() && !upload(p, p.d_es_poly32, g.es_poly32, st)))
         return fail(PSHT_ERR_NOMEM, "uploading kernel tables");
     if (!make_fft_table(p, p.fft_n2, g.N2, st) || !make_fft_table(p, p.fft_nt, g.Ntheta, st) ||
         !make_fft_table(p, p.fft_np, g.Nphi, st))

@@ -33,7 +33,8 @@ struct NufftArgs {
     const double *px, *py;
     const int32_t *perm;
     const int32_t *tile_start;
-    const double *poly;  // kernel polynomial table of the inner taps
+    const double *poly;    // kernel polynomial table of the inner taps (FP64 plans)
+    const float *poly32;   // the same in float (FP32 plans)
     TileGeom geo;
     // points whose stencil left their tile (never expected: the plan verifies
     // the sort; counted, not silently skipped)
@@ -67,31 +68,53 @@ __device__ inline double es_exp(double x) {
     return ldexp(p, (int)n);
 }
 
+// The same in float for the FP32 form: degree 7 (truncation below 5e-9
+// relative, under float rounding); the FP32 kernel exponent lies in
+// [-beta, 0] with beta <= 17 (W <= 7).
+__device__ inline float es_expf(float x) {
+    const float n = rintf(x * 1.44269504f);
+    const float r = fmaf(-n, 0.693147182f, x);
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)n);
+}
+
 // ES kernel psi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| <= 1, used for the
 // two edge taps (at most about 2e-5 at W = 11, larger for small W, where the
-// tolerance is correspondingly looser): the 3e-13 relative error of es_exp
-// stays far below epsilon for every kernel width.
+// tolerance is correspondingly looser): the error of the exponential stays
+// far below epsilon for every kernel width.
 __device__ inline double es_kernel(double z, double beta) {
     double t = fmax(0.0, 1.0 - z * z);
     return es_exp(beta * (sqrt(t) - 1.0));
 }
+__device__ inline float es_kernel(float z, float beta) {
+    float t = fmaxf(0.0f, 1.0f - z * z);
+    return es_expf(beta * (sqrtf(t) - 1.0f));
+}
 
 // Kernel weights of the W taps of a point with grid coordinate X and stencil
 // origin a0: tap i has psi((X - a0 - i) 2 / W).  With v = 2 (X - a0) - (W - 1)
-// in [-1, 1], the inner taps 1..(W-1)/2 are polynomials of degree
-// max(W + 1, 12) in v
-// from the plan's table C (power-major) and tap W - 1 - i is the same
-// polynomial at -v: even and odd parts by Horner in v^2 give both.  The two
-// edge taps use the formula.
+// in [-1, 1] (formed in double from the point's coordinate, then rounded to T),
+// the inner taps 1..(W-1)/2 are polynomials in v of degree
+// es_poly_degree(W, T is float) from the plan's table C (power-major) and tap
+// W - 1 - i is the same polynomial at -v: even and odd parts by Horner in v^2
+// give both.  The two edge taps use the formula.  T = float for the FP32 form
+// (weights and their products in float), double otherwise.
 // The table is wave-uniform: it is read through the scalar data cache into
 // SGPRs (constant address space), so the FMAs take it as scalar operands and
 // the LDS stays free for the tile subgrid.
 #if defined(__HIP_DEVICE_COMPILE__)
-typedef const __attribute__((address_space(4))) double *UniformPtr;
-__device__ inline UniformPtr uniform_ptr(const double *p) { return (UniformPtr)p; }
+template <typename T> using UniformPtr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ inline UniformPtr<T> uniform_ptr(const T *p) { return (UniformPtr<T>)p; }
 #else
-typedef const double *UniformPtr;
-__host__ __device__ inline UniformPtr uniform_ptr(const double *p) { return p; }
+template <typename T> using UniformPtr = const T *;
+template <typename T> __host__ __device__ inline UniformPtr<T> uniform_ptr(const T *p) { return p; }
 #endif
 
 // NS weight sets at once (the coordinates X[s] with origins a0[s] into k[s][]):
@@ -99,22 +122,22 @@ __host__ __device__ inline UniformPtr uniform_ptr(const double *p) { return p; }
 // a few coefficients are live in SGPRs at a time (evaluating the sets one after
 // another let the compiler hoist every coefficient and spill SGPRs into VGPR
 // lanes, one v_readlane per use).
-template <int W, int NS>
-__device__ inline void es_weights_n(const double *X, const int *a0, double beta, UniformPtr C, double (*k)[W]) {
-    constexpr int P = W + 1 > 12 ? W + 1 : 12, NC = (W - 1) / 2;
+template <typename T, int W, int NS>
+__device__ inline void es_weights_n(const double *X, const int *a0, T beta, UniformPtr<T> C, T (*k)[W]) {
+    constexpr int P = es_poly_degree(W, sizeof(T) == 4), NC = (W - 1) / 2;
     constexpr int PE = (P % 2 == 0) ? P : P - 1, PO = (P % 2 == 1) ? P : P - 1;
-    double v[NS], v2[NS];
+    T v[NS], v2[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        v[s] = 2.0 * (X[s] - (double)a0[s]) - (double)(W - 1);
+        v[s] = (T)(2.0 * (X[s] - (double)a0[s]) - (double)(W - 1));
         v2[s] = v[s] * v[s];
-        k[s][0] = es_kernel((v[s] + (double)(W - 1)) * (1.0 / W), beta);
-        k[s][W - 1] = es_kernel((v[s] - (double)(W - 1)) * (1.0 / W), beta);
+        k[s][0] = es_kernel((v[s] + (T)(W - 1)) * ((T)1 / (T)W), beta);
+        k[s][W - 1] = es_kernel((v[s] - (T)(W - 1)) * ((T)1 / (T)W), beta);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double e[NS], o[NS];
-        const double ce = C[PE * NC + c], co = C[PO * NC + c];
+        T e[NS], o[NS];
+        const T ce = C[PE * NC + c], co = C[PO * NC + c];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             e[s] = ce;
@@ -122,24 +145,28 @@ __device__ inline void es_weights_n(const double *X, const int *a0, double beta,
         }
 #pragma unroll
         for (int q = PE - 2; q >= 0; q -= 2) {
-            const double cq = C[q * NC + c];
+            const T cq = C[q * NC + c];
 #pragma unroll
             for (int s = 0; s < NS; ++s) e[s] = fma(e[s], v2[s], cq);
         }
 #pragma unroll
         for (int q = PO - 2; q >= 1; q -= 2) {
-            const double cq = C[q * NC + c];
+            const T cq = C[q * NC + c];
 #pragma unroll
             for (int s = 0; s < NS; ++s) o[s] = fma(o[s], v2[s], cq);
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double os = o[s] * v[s];
+            const T os = o[s] * v[s];
             k[s][c + 1] = e[s] + os;
             if (W - 2 - c != c + 1) k[s][W - 2 - c] = e[s] - os;
         }
     }
 }
+
+template <typename T> __device__ inline const T *table(const NufftArgs &a);
+template <> __device__ inline const double *table<double>(const NufftArgs &a) { return a.poly; }
+template <> __device__ inline const float *table<float>(const NufftArgs &a) { return a.poly32; }
 
 template <typename T> struct CplxT;
 template <> struct CplxT<double> { typedef double2 type; };
@@ -152,7 +179,7 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
     typedef typename CplxT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
     C *S = reinterpret_cast<C *>(smem);
-    const UniformPtr sC = uniform_ptr(a.poly);
+    const UniformPtr<T> sC = uniform_ptr(table<T>(a));
     const int t = blockIdx.x;
     const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
     if (p0 == p1) return;
@@ -184,30 +211,31 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
             atomicAdd(a.dropped, 1ull);
             continue;
         }
-        double kw[2][W];
+        // weights and sums in T: FP32 for the FP32 form
+        T kw[2][W];
         {
             const double xs[2] = {X, Y};
             const int os[2] = {a0, b0};
-            es_weights_n<W, 2>(xs, os, a.beta, sC, kw);
+            es_weights_n<T, W, 2>(xs, os, (T)a.beta, sC, kw);
         }
-        const double *kx = kw[0], *ky = kw[1];
-        double accr = 0.0, acci = 0.0;
+        const T *kx = kw[0], *ky = kw[1];
+        T accr = 0, acci = 0;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             const C *Srow = S + (li + i) * SYP + lj;
-            double rr = 0.0, ri = 0.0;
+            T rr = 0, ri = 0;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 C v = Srow[j];
-                rr = fma(ky[j], (double)v.x, rr);
-                ri = fma(ky[j], (double)v.y, ri);
+                rr = fma(ky[j], v.x, rr);
+                ri = fma(ky[j], v.y, ri);
             }
             accr = fma(kx[i], rr, accr);
             acci = fma(kx[i], ri, acci);
         }
         C out;
-        out.x = (T)accr;
-        out.y = (T)acci;
+        out.x = accr;
+        out.y = acci;
         map[pm] = out;
     }
 }
@@ -227,7 +255,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
     // precisions: the FP64 LDS atomic add is a native fast path on gfx950,
     // while FP32 LDS atomic adds measured an order of magnitude slower.
     double *Sre = reinterpret_cast<double *>(smem), *Sim = Sre + SX * SYP;
-    const UniformPtr sC = uniform_ptr(a.poly);
+    const UniformPtr<T> sC = uniform_ptr(table<T>(a));
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
     for (int e = threadIdx.x; e < 2 * SX * SYP; e += kTileThreads) Sre[e] = 0.0;
     __syncthreads();
@@ -243,29 +271,31 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
             atomicAdd(a.dropped, (a.perm[p + 1] >= 0) ? 2ull : 1ull);
             continue;
         }
-        double kw[4][W];
+        // weights and the slot's per-cell sums in T (FP32 for the FP32 form);
+        // the subgrid accumulates in double
+        T kw[4][W];
         {
             // the partner has the same cell, but its own unwrapped origin: across
             // phi = 0 its b0 differs from this point's by Nphi
             const double xs[4] = {X, Y, X2, Y2};
             const int os[4] = {a0, b0, stencil_origin(X2, W), stencil_origin(Y2, W)};
-            es_weights_n<W, 4>(xs, os, a.beta, sC, kw);
+            es_weights_n<T, W, 4>(xs, os, (T)a.beta, sC, kw);
         }
-        const double *kx = kw[0], *ky = kw[1], *kx2 = kw[2], *ky2 = kw[3];
+        const T *kx = kw[0], *ky = kw[1], *kx2 = kw[2], *ky2 = kw[3];
         const C f = map[a.perm[p]];
         const int pm2 = a.perm[p + 1];
         C f2;
         f2.x = f2.y = (T)0;
         if (pm2 >= 0) f2 = map[pm2];
-        const double fr = f.x, fi = f.y, fr2 = f2.x, fi2 = f2.y;
+        const T fr = f.x, fi = f.y, fr2 = f2.x, fi2 = f2.y;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             double *Rre = Sre + (li + i) * SYP + lj, *Rim = Sim + (li + i) * SYP + lj;
-            const double wr = kx[i] * fr, wi = kx[i] * fi, wr2 = kx2[i] * fr2, wi2 = kx2[i] * fi2;
+            const T wr = kx[i] * fr, wi = kx[i] * fi, wr2 = kx2[i] * fr2, wi2 = kx2[i] * fi2;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(Rre + j, fma(wr, ky[j], wr2 * ky2[j]));
-                atomicAdd(Rim + j, fma(wi, ky[j], wi2 * ky2[j]));
+                atomicAdd(Rre + j, (double)fma(wr, ky[j], wr2 * ky2[j]));
+                atomicAdd(Rim + j, (double)fma(wi, ky[j], wi2 * ky2[j]));
             }
         }
     }
@@ -299,6 +329,7 @@ static NufftArgs nufft_args(const psht_plan_s &p) {
     a.perm = p.d_perm;
     a.tile_start = p.d_tile_start;
     a.poly = p.d_es_poly;
+    a.poly32 = p.d_es_poly32;
     a.geo = tile_geom(p);
     a.dropped = p.d_dropped;
     return a;

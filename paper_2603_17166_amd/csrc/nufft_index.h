@@ -29,6 +29,13 @@ struct TileGeom {
 
 PSHT_HD inline int stencil_origin(double X, int W) { return (int)ceil(X - 0.5 * W); }
 
+// Degree of the polynomial kernel table of the inner taps: FP64 plans
+// max(W + 1, 12); FP32 plans, whose table is evaluated in float,
+// max(W + 2, 10) (its float evaluation error is about 1e-7).
+PSHT_HD constexpr int es_poly_degree(int W, bool fp32) {
+    return fp32 ? (W + 2 > 10 ? W + 2 : 10) : (W + 1 > 12 ? W + 1 : 12);
+}
+
 // b0 reduced to [0, Nphi).
 PSHT_HD inline int wrap_col(int b0, int Nphi) {
     int b = b0 % Nphi;

@@ -9,6 +9,7 @@
 #include <thread>
 
 #include "leg_common.h"
+#include "nufft_index.h"
 #include "psht_internal.h"
 
 namespace psht {
@@ -132,14 +133,17 @@ static ld es_psi(ld z, ld beta) {
 // v = 2 (X - a0) - (W - 1) in [-1, 1], tap i has weight g_i(v) = psi(z) with
 // z = (v + W - 1 - 2 i) / W; tap W - 1 - i is g_i(-v).  Each inner tap
 // i = 1..(W-1)/2 is interpolated at the P + 1 Chebyshev points of [-1, 1]
-// (degree P = max(W + 1, 12)), converted to powers of v, and checked against psi on a
+// (degree P = es_poly_degree: max(W + 1, 12)), converted to powers of v, and checked against psi on a
 // fine grid with the device's evaluation order (even and odd parts by Horner
 // in v^2).  The two edge taps reach |z| = 1, where sqrt(1 - z^2) has a
 // vertical tangent that polynomials resolve slowly; they keep the formula.
+// FP32 plans get the table in float, of degree max(W + 2, 10), checked in
+// float arithmetic.
 static void es_poly_table(Geometry &g) {
-    const int W = g.W, P = W + 1 > 12 ? W + 1 : 12, NC = (W - 1) / 2, n = P + 1;
+    const int W = g.W, P = es_poly_degree(W, g.fp32), NC = (W - 1) / 2, n = P + 1;
     const ld beta = g.beta;
     g.es_poly.assign((size_t)n * NC, 0.0);
+    g.es_poly32.assign(g.fp32 ? (size_t)n * NC : 0, 0.0f);
     double worst = 0;
     for (int c = 0; c < NC; ++c) {
         const int i = c + 1;
@@ -169,8 +173,24 @@ static void es_poly_table(Geometry &g) {
             t1 = t2;
         }
         for (int q = 0; q < n; ++q) g.es_poly[(size_t)q * NC + c] = (double)mono[q];
-        // check in double, in the device's order
         const int PE = (P % 2 == 0) ? P : P - 1, PO = (P % 2 == 1) ? P : P - 1;
+        if (g.fp32) {
+            // check in float, in the device's order
+            for (int q = 0; q < n; ++q) g.es_poly32[(size_t)q * NC + c] = (float)mono[q];
+            const float *C = g.es_poly32.data();
+            for (int t = 0; t <= 400; ++t) {
+                const float v = -1.0f + t / 200.0f, v2 = v * v;
+                float e = C[(size_t)PE * NC + c];
+                for (int q = PE - 2; q >= 0; q -= 2) e = std::fma(e, v2, C[(size_t)q * NC + c]);
+                float o = C[(size_t)PO * NC + c];
+                for (int q = PO - 2; q >= 1; q -= 2) o = std::fma(o, v2, C[(size_t)q * NC + c]);
+                o *= v;
+                worst = std::max(worst, (double)fabsl((ld)(e + o) - f(v)));
+                worst = std::max(worst, (double)fabsl((ld)(e - o) - f(-v)));
+            }
+            continue;
+        }
+        // check in double, in the device's order
         for (int t = 0; t <= 400; ++t) {
             const double v = -1.0 + t / 200.0, v2 = v * v;
             double e = g.es_poly[(size_t)PE * NC + c];
@@ -360,7 +380,7 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
     g.beta = es_beta(g.W);
     g.sigma = 2.0;
     es_poly_table(g);
-    if (g.es_poly_err > std::max(1e-3 * eps, 1e-14)) {
+    if (g.es_poly_err > std::max(1e-3 * eps, g.fp32 ? 2e-7 : 1e-14)) {
         err = {PSHT_ERR_UNSUPPORTED, "kernel polynomial table not accurate enough"};
         return false;
     }

@@ -50,6 +50,7 @@ struct Geometry {
     // (power-major); the mirror taps follow from v -> -v.  es_poly_err:
     // largest error on a test grid.
     std::vector<double> es_poly;
+    std::vector<float> es_poly32;  // FP32 plans: the table in float (degree es_poly_degree(W, true))
     double es_poly_err = 0;
     double predicted_speedup = 0;
     double legendre_triples = 0;
@@ -153,6 +154,7 @@ struct psht_plan_s {
     // NUFFT tables
     double *d_psihat_t = nullptr, *d_psihat_p = nullptr;
     double *d_es_poly = nullptr;
+    float *d_es_poly32 = nullptr;
     psht::FftTable fft_n2, fft_nt, fft_np, fft_np_half;
     bool phi_split = false;
     // points, sorted by tile

@@ -189,9 +189,15 @@ def test_invalid_arguments():
 
 
 @pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-5, 1e-6, 1e-8, 1e-10, 1e-12, 1e-14])
-def test_kernel_polynomial_table_accuracy(eps):
+@pytest.mark.parametrize("prec", ["auto", "fp64"])
+def test_kernel_polynomial_table_accuracy(eps, prec):
     """The inner ES kernel taps are evaluated from polynomials; the plan
     checks them against the kernel formula on a fine grid (both signs of the
-    offset) and reports the largest error, which must stay far below eps."""
-    info = plan_geometry(256, 2, 0.3, eps, "auto")[0]
-    assert 0.0 < info["kernel_poly_err"] <= max(1e-3 * eps, 1e-14)
+    offset) in the arithmetic the kernels use, and reports the largest error,
+    which must stay below eps: 1e-3 eps for the FP64 table, and for the float
+    table of the FP32 form (eps >= 1e-6 under "auto") the larger of that and
+    2e-7, the float evaluation's own level."""
+    info = plan_geometry(256, 2, 0.3, eps, prec)[0]
+    bound = max(1e-3 * eps, 2e-7 if info["map_is_fp32"] else 1e-14)
+    assert bool(info["map_is_fp32"]) == (prec == "auto" and eps >= 1e-6)
+    assert 0.0 < info["kernel_poly_err"] <= bound
