@@ -372,6 +372,45 @@ def autograd_step(steps: int, log) -> dict:
             "note": "forward synthesis + loss + backward (adjoint kernel) per step"}
 
 
+def full_sky_speedup(workloads, steps: int, log) -> dict:
+    """The partial-sky method against the full-sky mode (rings over the whole
+    sphere, Lmax = lmax) on the same points, coefficients and accuracy: one
+    synthesis + one adjoint each, and the speed-up beside the plan's predicted
+    one, 1 / ((1 + eps_apo)(1 - cos theta_max)), the estimate of Table I's
+    'predicted' column."""
+    import torch
+
+    from paper_2603_17166_amd.plan import Plan
+
+    out = {}
+    for w in workloads:
+        a = torch.as_tensor(w.alm(), device="cuda")
+        res = {}
+        for mode in ("partial", "full_sky"):
+            plan = Plan(w.theta, w.phi, w.lmax, w.spin, w.epsilon, w.precision, full_sky=(mode == "full_sky"))
+            fmap = torch.as_tensor(w.adjoint_map(np.complex64 if plan.info["map_is_fp32"] else np.complex128),
+                                   device="cuda")
+            om = torch.empty(w.npoints, dtype=plan.map_dtype, device="cuda")
+            oa = torch.empty_like(a)
+            plan.workspace(1)
+            time_steps(plan, a, fmap, om, oa, 1, "both")
+            t = time_steps(plan, a, fmap, om, oa, steps, "both")
+            res[mode] = {"ms_per_step": t * 1e3 / steps, "Lmax": plan.info["Lmax"],
+                         "legendre_triples": plan.info["legendre_triples"],
+                         "predicted_speedup": plan.info["predicted_speedup"]}
+            plan.close()
+        sp = res["full_sky"]["ms_per_step"] / res["partial"]["ms_per_step"]
+        out[w.name] = {"partial_ms": res["partial"]["ms_per_step"], "full_sky_ms": res["full_sky"]["ms_per_step"],
+                       "speedup": sp, "predicted_speedup": res["partial"]["predicted_speedup"],
+                       "Lmax": [res["partial"]["Lmax"], res["full_sky"]["Lmax"]],
+                       "legendre_triples_ratio": res["full_sky"]["legendre_triples"] /
+                       res["partial"]["legendre_triples"]}
+        log("full sky vs partial %s: %.3f vs %.3f ms, speed-up %.2f (predicted %.2f)" % (
+            w.name, res["full_sky"]["ms_per_step"], res["partial"]["ms_per_step"], sp,
+            res["partial"]["predicted_speedup"]))
+    return out
+
+
 def batched_maps(w, nmaps: int, steps: int, check_points: int, log) -> dict:
     """nmaps coefficient sets / maps per call on one plan (the Legendre
     synthesis runs as one MFMA pass per group of up to 8 maps)."""
@@ -545,6 +584,7 @@ def main() -> int:
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of saturation")
     ap.add_argument("--serve-fp64-single", type=int, default=300,
                     help="requests of the served mix also run one at a time on FP64 plans")
+    ap.add_argument("--full-sky-only", action="store_true", help="only the full-sky vs partial comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -566,6 +606,9 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
+        return 0
+    if args.full_sky_only:
+        print(json.dumps(full_sky_speedup([syn.spt_like(2048), syn.spt_fine("fp64")], 3, log)), flush=True)
         return 0
     metric = "synth+adjoint points/s at eps=1e-10 FP64 vs eps=1e-5 FP32; p50/p99 latency"
     base = {"metric": metric, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -619,6 +662,7 @@ def main() -> int:
         ex["batched_maps"]["speedup_per_map"] = ex["batched_maps"]["points_per_s"] / \
             ex["spt1658-l2048-s2-fp64"]["points_per_s"]
         line["other_workloads"] = ex
+        line["full_sky_vs_partial"] = full_sky_speedup([w2, syn.spt_fine("fp64")], 3, log)
         line["served"] = served(args.serve_requests, args.serve_load, log, args.serve_fp64_single)
         if "served_vs_fp64_single" in line["served"]:
             line["served_vs_fp64_single"] = line["served"]["served_vs_fp64_single"]

@@ -105,6 +105,30 @@ typedef struct {
     int64_t adj_states;
 } psht_plan_info;
 
+/* Options of psht_plan_create_ex / psht_plan_geometry_ex (NULL: all defaults,
+ * the behaviour of psht_plan_create).
+ *   full_sky : 1 selects the full-sky mode: rings over the whole sphere,
+ *              theta_max = pi, window w = 1, Lmax = lmax rounded up to a
+ *              smooth 2 Lmax + 1 (the Fourier-sphere synthesis of Sec. I.B
+ *              without the partial-sky steps of Sec. II); exact up to the
+ *              NUFFT error for any point set.  0: partial sky (the mode falls
+ *              back to the full sky only when the patch is too large to gain).
+ *   window   : apodization bell of Sec. II.C: PSHT_WINDOW_ES (0, the
+ *              exponential-of-semicircle bell) or PSHT_WINDOW_KB (1, the
+ *              Kaiser-Bessel bell).
+ *   cl, cl_lmax : optional host array cl[0..cl_lmax] (cl_lmax >= lmax), the
+ *              power spectrum C_l of the fields to be transformed; when given,
+ *              Lmax is the smallest smooth value whose predicted isotropic
+ *              error (Sec. II.D) stays below epsilon, instead of eq. Lmax2.
+ *              NULL / 0: eq. Lmax2. */
+typedef struct {
+    int32_t full_sky;
+    int32_t window;
+    const double *cl;
+    int32_t cl_lmax;
+} psht_plan_options;
+enum { PSHT_WINDOW_ES = 0, PSHT_WINDOW_KB = 1 };
+
 /* Build a plan for npoints points (device arrays theta, phi; read during the
  * call only, not kept).  Validates lmax >= 0, 0 <= spin <= lmax,
  * 1e-14 <= epsilon <= 1e-2, npoints >= 0 and < 2^30, every theta in
@@ -116,6 +140,11 @@ typedef struct {
 psht_status psht_plan_create(psht_plan *out, int lmax, int spin, int64_t npoints,
                              const double *theta, const double *phi,
                              double epsilon, int precision, void *hip_stream);
+
+/* psht_plan_create with options (see psht_plan_options; opts may be NULL). */
+psht_status psht_plan_create_ex(psht_plan *out, int lmax, int spin, int64_t npoints,
+                                const double *theta, const double *phi, double epsilon, int precision,
+                                const psht_plan_options *opts, void *hip_stream);
 
 /* Copy the plan's parameters into *info. */
 psht_status psht_plan_query(psht_plan plan, psht_plan_info *info);
@@ -196,6 +225,11 @@ psht_status psht_plan_check(psht_plan plan, int64_t *dropped, void *hip_stream);
 psht_status psht_plan_geometry(int lmax, int spin, double theta_star, double epsilon, int precision,
                                psht_plan_info *info, double *ring_theta, double *ring_weight,
                                int32_t *ring_mmax, int capacity);
+
+/* psht_plan_geometry with options (see psht_plan_options; opts may be NULL). */
+psht_status psht_plan_geometry_ex(int lmax, int spin, double theta_star, double epsilon, int precision,
+                                  const psht_plan_options *opts, psht_plan_info *info, double *ring_theta,
+                                  double *ring_weight, int32_t *ring_mmax, int capacity);
 
 /* ---- Stage-level entry points (diagnostics and stage tests) ----------------
  * Run a single stage of a plan on device buffers.  Layouts:

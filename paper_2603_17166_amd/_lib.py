@@ -30,7 +30,7 @@ EXPORTS = (
     "psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_destroy",
     "psht_last_error", "psht_plan_geometry", "psht_stage", "psht_fft", "psht_legendre_column",
     "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc",
-    "psht_plan_check",
+    "psht_plan_check", "psht_plan_create_ex", "psht_plan_geometry_ex",
 )
 
 STAGE_NAMES = ("leg_synth", "theta_synth", "phi_synth", "interp", "grid_zero", "spread", "phi_adj", "theta_adj",
@@ -57,6 +57,14 @@ class PlanInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+WINDOWS = {"es": 0, "kb": 1}
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("full_sky", ctypes.c_int32), ("window", ctypes.c_int32), ("cl", ctypes.POINTER(ctypes.c_double)),
+                ("cl_lmax", ctypes.c_int32)]
+
+
 class PshtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("psht error %d: %s" % (code, msg))
@@ -77,6 +85,11 @@ def load() -> ctypes.CDLL:
     i32p = ctypes.POINTER(ctypes.c_int32)
     lib.psht_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp,
                                      ctypes.c_double, ctypes.c_int, vp]
+    lib.psht_plan_create_ex.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp,
+                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(PlanOptions), vp]
+    lib.psht_plan_geometry_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                          ctypes.POINTER(PlanOptions), ctypes.POINTER(PlanInfo), dp, dp, i32p,
+                                          ctypes.c_int]
     lib.psht_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.psht_synth.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
@@ -97,7 +110,8 @@ def load() -> ctypes.CDLL:
     lib.psht_plan_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     for name in ("psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_geometry",
                  "psht_stage", "psht_fft", "psht_legendre_column", "psht_plan_set_timing", "psht_plan_timing",
-                 "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc", "psht_plan_check"):
+                 "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc", "psht_plan_check",
+                 "psht_plan_create_ex", "psht_plan_geometry_ex"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

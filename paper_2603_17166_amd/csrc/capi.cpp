@@ -150,6 +150,9 @@ struct ScopedDevFree {
 // a third of the average work per wave slot (two waves per SIMD): with
 // longest-first placement the last items then finish close together.
 // Segments k >= 1 start from stored states (40 bytes per ring and segment).
+// An order with more active rings than one item holds (1536 at G = 4: the
+// full sky above lmax ~ 3000, the partial sky near lmax 10000) is cut into
+// ring groups; their items add into the output, which is cleared first.
 bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error &err) {
     const psht::Geometry &g = p.g;
     const int lmax = g.lmax, s = g.spin, M = g.mmax;
@@ -170,8 +173,9 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
     }
     auto rings_per_lane = [&](int m) {
         if (first[m] < 0) return 0;
-        const int nr = last[m] - first[m] + 1;
-        return (nr + 64 * G - 1) / (64 * G);
+        const int nr = last[m] - first[m] + 1, gm = 64 * psht::kAdjMaxRings * G;
+        const int ng = (nr + gm - 1) / gm, gsize = (nr + ng - 1) / ng;
+        return (gsize + 64 * G - 1) / (64 * G);
     };
     double total = 0.0;
     int rmax = 1;
@@ -187,21 +191,35 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
         const int v = atoi(e);
         if (v >= 8 && v <= 1 << 16) S = v;
     }
+    // Orders with more rings than one item holds (64 x 6 x G) are cut into
+    // ring groups whose items add into a cleared output (see adj_accumulate).
+    int group_max = 64 * psht::kAdjMaxRings * G;
+    if (const char *e = getenv("PSHT_ADJ_GROUP")) {  // tests and tuning runs: smaller ring groups
+        const int v = atoi(e);
+        if (v >= 1 && v < group_max) group_max = v;
+    }
+    bool accumulate = false;
     std::vector<psht::AdjItem> items;
     std::vector<psht::StateItem> sitems;
     int64_t off = 0;
     for (int m = 0; m <= M; ++m) {
         const int l0 = std::max(m, s);
-        const int R = rings_per_lane(m);
-        if (R == 0) {
+        if (first[m] < 0) {
             items.push_back(psht::AdjItem{m, 0, 0, m, lmax + 1, 0, -1});
             continue;
         }
         const int jb = first[m], je = last[m] + 1, nr = je - jb;
+        const int ng = (nr + group_max - 1) / group_max, gsize = (nr + ng - 1) / ng;
+        accumulate |= ng > 1;
         const int nseg = (lmax + 1 - l0 + S - 1) / S;
         for (int k = 0; k < nseg; ++k) {
             const int la = l0 + k * S, lb = std::min(lmax + 1, la + S);
-            items.push_back(psht::AdjItem{m, jb, je, la, lb, R, k == 0 ? -1 : off + (int64_t)(k - 1) * nr});
+            for (int q = 0; q < ng; ++q) {
+                const int gb = jb + q * gsize, ge = std::min(je, gb + gsize);
+                const int R = (ge - gb + 64 * G - 1) / (64 * G);
+                items.push_back(psht::AdjItem{m, gb, ge, la, lb, R,
+                                              k == 0 ? -1 : off + (int64_t)(k - 1) * nr + (gb - jb)});
+            }
         }
         if (nseg > 1) {
             for (int j0 = jb; j0 < je; j0 += 64) sitems.push_back(psht::StateItem{m, j0, jb, je, nseg, S, off});
@@ -214,6 +232,7 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
     });
     p.adj_waves = G;
     p.adj_rmax = rmax;
+    p.adj_accumulate = accumulate;
     p.adj_seg = S;
     p.n_adj_states = off;
     p.alm_tail = (int64_t)(M + 1) * (2 * lmax + 1 - (M + 1)) / 2 + (M + 1);  // index(l = M + 1, m = M + 1)
@@ -238,7 +257,8 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
 }
 
 psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
-                             const double *phi, double epsilon, int precision, hipStream_t st) {
+                             const double *phi, double epsilon, int precision, const psht_plan_options *opts,
+                             hipStream_t st) {
     if (!out) return fail(PSHT_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (lmax < 0 || spin < 0 || spin > lmax) return fail(PSHT_ERR_ARG, "need lmax >= 0 and 0 <= spin <= lmax");
@@ -278,16 +298,22 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     psht_plan_s &p = *plan;
     p.npts = npoints;
     psht::Error err;
-    if (!psht::geometry_compute(p.g, lmax, spin, tmax, tmin, epsilon, precision, true, err)) return fail(err);
+    if (!psht::geometry_compute(p.g, lmax, spin, tmax, tmin, epsilon, precision, true, err, true, opts))
+        return fail(err);
     const psht::Geometry &g = p.g;
     const bool fp32 = g.fp32;
     const int fmax = fp32 ? psht::kFftMaxLds32 : psht::kFftMaxLds64;
-    if (g.Ntheta > fmax || g.N2 > fmax)
-        return fail(PSHT_ERR_UNSUPPORTED, "Theta grid of " + std::to_string(g.Ntheta) + " exceeds the LDS FFT limit");
-    // Rows longer than the 2560-point tier run as two half-length transforms in
-    // workgroups of their own (twice the transforms in flight per CU); Nphi is even.
-    p.phi_split = g.Nphi > fmax || (g.Nphi > 2560 && g.Nphi % 2 == 0);
-    if (p.phi_split && g.Nphi / 2 > fmax)
+    // The Theta grid (NT = 2 N2 points) above the LDS limit runs as two N2-point
+    // transforms (even and odd rows); N2 itself must fit.
+    if (g.N2 > fmax)
+        return fail(PSHT_ERR_UNSUPPORTED, "Theta circle of " + std::to_string(g.N2) + " samples exceeds the LDS FFT limit");
+    p.theta_split = g.Ntheta > fmax;
+    if (const char *e = getenv("PSHT_THETA_SPLIT"))  // tests and tuning runs: 1 forces the split where possible
+        if (atoi(e) == 1 && g.Ntheta == 2 * g.N2) p.theta_split = true;
+    if (p.theta_split && g.Ntheta != 2 * g.N2)
+        return fail(PSHT_ERR_UNSUPPORTED, "Theta grid above the LDS limit that is not twice the circle");
+    // phi rows run as g.phi_parts transforms of Nphi / phi_parts points (see params.cpp)
+    if (g.Nphi / g.phi_parts > fmax)
         return fail(PSHT_ERR_UNSUPPORTED, "phi grid of " + std::to_string(g.Nphi) + " exceeds the LDS FFT limit");
 
     p.leg = psht::leg_table_get(lmax, spin, err);
@@ -402,7 +428,8 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     if (!make_fft_table(p, p.fft_n2, g.N2, st) || !make_fft_table(p, p.fft_nt, g.Ntheta, st) ||
         !make_fft_table(p, p.fft_np, g.Nphi, st))
         return fail(PSHT_ERR_NOMEM, "FFT tables");
-    if (p.phi_split && !make_fft_table(p, p.fft_np_half, g.Nphi / 2, st)) return fail(PSHT_ERR_NOMEM, "FFT tables");
+    if (g.phi_parts > 1 && !make_fft_table(p, p.fft_np_part, g.Nphi / g.phi_parts, st))
+        return fail(PSHT_ERR_NOMEM, "FFT tables");
 
     // points: bucket sort into tiles (PSHT_TILE="<rows>x<cols>" overrides the tile shape for tuning runs)
     if (const char *ts = getenv("PSHT_TILE")) {
@@ -493,8 +520,14 @@ extern "C" {
 
 psht_status psht_plan_create(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
                              const double *phi, double epsilon, int precision, void *hip_stream) {
+    return psht_plan_create_ex(out, lmax, spin, npoints, theta, phi, epsilon, precision, nullptr, hip_stream);
+}
+
+psht_status psht_plan_create_ex(psht_plan *out, int lmax, int spin, int64_t npoints, const double *theta,
+                                const double *phi, double epsilon, int precision, const psht_plan_options *opts,
+                                void *hip_stream) {
     try {
-        return plan_create_impl(out, lmax, spin, npoints, theta, phi, epsilon, precision,
+        return plan_create_impl(out, lmax, spin, npoints, theta, phi, epsilon, precision, opts,
                                 static_cast<hipStream_t>(hip_stream));
     } catch (const std::bad_alloc &) {
         return fail(PSHT_ERR_NOMEM, "host allocation failed");
@@ -682,13 +715,21 @@ psht_status psht_plan_check(psht_plan plan, int64_t *dropped, void *hip_stream) 
 psht_status psht_plan_geometry(int lmax, int spin, double theta_star, double epsilon, int precision,
                                psht_plan_info *info, double *ring_theta, double *ring_weight, int32_t *ring_mmax,
                                int capacity) {
+    return psht_plan_geometry_ex(lmax, spin, theta_star, epsilon, precision, nullptr, info, ring_theta, ring_weight,
+                                 ring_mmax, capacity);
+}
+
+psht_status psht_plan_geometry_ex(int lmax, int spin, double theta_star, double epsilon, int precision,
+                                  const psht_plan_options *opts, psht_plan_info *info, double *ring_theta,
+                                  double *ring_weight, int32_t *ring_mmax, int capacity) {
     try {
         if (!info) return fail(PSHT_ERR_ARG, "info is NULL");
         if (capacity < 0 || (capacity > 0 && (!ring_theta || !ring_weight || !ring_mmax)))
             return fail(PSHT_ERR_ARG, "ring arrays are NULL");
         psht_plan_s p;
         psht::Error err;
-        if (!psht::geometry_compute(p.g, lmax, spin, theta_star, 0.0, epsilon, precision, false, err, capacity > 0))
+        if (!psht::geometry_compute(p.g, lmax, spin, theta_star, 0.0, epsilon, precision, false, err, capacity > 0,
+                                    opts))
             return fail(err);
         fill_info(p, info);
         info->workspace_bytes_per_map = 0;

@@ -146,7 +146,8 @@ template <typename C, int R> __device__ inline void dft(C *v, int sign) {
 // longest tier holds up to 128 KB of LDS, one workgroup per CU: 1024 threads
 // give each SIMD four waves.
 template <typename T> __host__ __device__ constexpr int fft_threads(int maxn) {
-    if constexpr (sizeof(T) == 8) return maxn <= 2560 ? 256 : (maxn <= 4096 ? 512 : 1024);
+    // (the 10240-point tier fills the 160 KB of LDS a gfx950 workgroup may use)
+    if constexpr (sizeof(T) == 8) return maxn <= 2560 ? 256 : (maxn <= 4096 ? 512 : (maxn <= 8192 ? 1024 : 512));
     // FP32 data takes half the LDS per transform: the longest tier (64 KB) fits
     // two workgroups of 512 threads per CU (FP32 phi halves at lmax 4096:
     // 0.15 -> 0.13 ms each way); 256 threads up to 4096 points made the Theta
@@ -241,7 +242,8 @@ struct StageArgs {
     FftDev fn2, fnt, fnp;
     const double2 *tw_n2, *tw_nt, *tw_np, *tw_np_full;
     int L, N2, NT, Nphi, nring, mmax, spin, row_lo, rows_used;
-    bool split;  // phi FFT as two half-length transforms
+    int parts;    // phi FFT as this many transforms of length Nphi / parts (1, 2 or 4)
+    bool tsplit;  // Theta grid transform (NT = 2 N2 points) as two N2-point transforms (even / odd rows)
     const double *ring_w;
     const int32_t *ring_mmax;
     const double *psihat_t, *psihat_p;
@@ -259,6 +261,17 @@ __device__ inline int xcd_column(int b, int ncol) {
 }
 
 static inline unsigned xcd_grid(int ncol) { return 8u * (unsigned)((ncol + 7) / 8); }
+
+// The Theta-grid transform of length NT = 2 N2 as two N2-point transforms:
+// with the spectrum X_n, |n| <= L < N2 / 2, held at n mod N2, the grid rows
+// k = 2 k' + h are sum_n (X_n e^{2 pi i n h / NT}) e^{2 pi i n k' / N2}; the
+// adjoint's spectrum is sum_h e^{-2 pi i n h / NT} FFT_N2(rows 2 k' + h)[n].
+// Each thread keeps its entries i = tid + q NTHR of the spectrum in
+// registers between the two halves.
+template <typename T, int MAXN> struct ThetaHalves {
+    static constexpr int NTHR = fft_threads<T>(MAXN);
+    static constexpr int NQ = (MAXN + NTHR - 1) / NTHR;
+};
 
 template <typename T, int MAXN>
 __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_synth(StageArgs a, const double2 *F,
@@ -284,6 +297,7 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_synth(StageArgs 
     }
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fn2, -1, a.tw_n2);  // N2 * Fourier coefficient
+    const int64_t ldv = 2 * a.mmax + 1;
     // divide by N2 psihat(|n|) and pad to NT: n < 0 moves from N2 - |n| to NT - |n|
     for (int n = 1 + threadIdx.x; n <= L; n += fft_threads<T>(MAXN))
         buf[NT - n] = cscale(buf[N2 - n], (T)(1.0 / (N2 * a.psihat_t[n])));
@@ -299,11 +313,68 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_synth(StageArgs 
     }
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnt, +1, a.tw_nt);
-    const int64_t ldv = 2 * a.mmax + 1;
     for (int r = threadIdx.x; r < a.rows_used; r += fft_threads<T>(MAXN)) {
         int row = (a.row_lo + r) % NT;
         if (row < 0) row += NT;
         V[(int64_t)r * ldv + mi] = buf[row];
+    }
+}
+
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_synth_split(StageArgs a, const double2 *F,
+                                                             typename CT<T>::type *V) {
+    typedef typename CT<T>::type C;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *buf = reinterpret_cast<C *>(smem);
+    const int mi = xcd_column(blockIdx.x, 2 * a.mmax + 1);
+    if (mi > 2 * a.mmax) return;
+    const int am = abs(mi - a.mmax);
+    const double sig = ((a.spin + am) & 1) ? -1.0 : 1.0;  // mirror sign (-1)^(s+m)
+    const int L = a.L, N2 = a.N2, NT = a.NT;
+    const double2 *Fm = F + (int64_t)mi * a.nring;
+    for (int k = threadIdx.x; k < N2; k += fft_threads<T>(MAXN)) {
+        const int j = k <= L ? k : N2 - k;
+        const double wj = (k <= L ? 1.0 : sig) * a.ring_w[j];
+        double2 v = make_double2(0.0, 0.0);
+        if (a.ring_mmax[j] >= am) v = Fm[j];
+        C c;
+        c.x = (T)(v.x * wj);
+        c.y = (T)(v.y * wj);
+        buf[k] = c;
+    }
+    __syncthreads();
+    lds_fft<T, MAXN>(buf, a.fn2, -1, a.tw_n2);  // N2 * Fourier coefficient
+    const int64_t ldv = 2 * a.mmax + 1;
+    {
+        typedef ThetaHalves<T, MAXN> H;
+        C spec[H::NQ];
+#pragma unroll
+        for (int q = 0; q < H::NQ; ++q) {
+            const int i = threadIdx.x + q * H::NTHR;
+            if (i < N2) {
+                const int n = i <= L ? i : N2 - i;  // |n|
+                spec[q] = cscale(buf[i], (T)(1.0 / (N2 * a.psihat_t[n])));
+            }
+        }
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < H::NQ; ++q) {
+                const int i = threadIdx.x + q * H::NTHR;
+                if (i < N2) {
+                    C v = spec[q];
+                    if (h) v = cmul(v, twiddle<C>(a.tw_nt, i <= L ? i : i - N2 + NT, +1));  // e^{2 pi i n / NT}
+                    buf[i] = v;
+                }
+            }
+            __syncthreads();
+            lds_fft<T, MAXN>(buf, a.fn2, +1, a.tw_n2);
+            for (int r = threadIdx.x; r < a.rows_used; r += H::NTHR) {
+                int row = (a.row_lo + r) % NT;
+                if (row < 0) row += NT;
+                if ((row & 1) == h) V[(int64_t)r * ldv + mi] = buf[row >> 1];
+            }
+        }
     }
 }
 
@@ -352,33 +423,98 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_adjoint(StageArg
     }
 }
 
+template <typename T, int MAXN>
+__global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_adjoint_split(StageArgs a, const typename CT<T>::type *V,
+                                                               double2 *F) {
+    typedef typename CT<T>::type C;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *buf = reinterpret_cast<C *>(smem);
+    const int mi = xcd_column(blockIdx.x, 2 * a.mmax + 1);
+    if (mi > 2 * a.mmax) return;
+    const int am = abs(mi - a.mmax);
+    const double sig = ((a.spin + am) & 1) ? -1.0 : 1.0;
+    const int L = a.L, N2 = a.N2, NT = a.NT;
+    const int64_t ldv = 2 * a.mmax + 1;
+    C z;
+    z.x = z.y = (T)0;
+    {
+        typedef ThetaHalves<T, MAXN> H;
+        C spec[H::NQ];
+        for (int h = 0; h < 2; ++h) {
+            for (int k = threadIdx.x; k < N2; k += H::NTHR) buf[k] = z;
+            __syncthreads();
+            for (int r = threadIdx.x; r < a.rows_used; r += H::NTHR) {
+                int row = (a.row_lo + r) % NT;
+                if (row < 0) row += NT;
+                if ((row & 1) == h) buf[row >> 1] = V[(int64_t)r * ldv + mi];
+            }
+            __syncthreads();
+            lds_fft<T, MAXN>(buf, a.fn2, -1, a.tw_n2);
+#pragma unroll
+            for (int q = 0; q < H::NQ; ++q) {
+                const int i = threadIdx.x + q * H::NTHR;
+                if (i < N2) {
+                    C v = buf[i];
+                    if (h) spec[q] = cadd(spec[q], cmul(v, twiddle<C>(a.tw_nt, i <= L ? i : i - N2 + NT, -1)));
+                    else spec[q] = v;
+                }
+            }
+            __syncthreads();
+        }
+        // divide by N2 psihat(|n|); the spectrum already sits at n mod N2
+#pragma unroll
+        for (int q = 0; q < H::NQ; ++q) {
+            const int i = threadIdx.x + q * H::NTHR;
+            if (i < N2) buf[i] = cscale(spec[q], (T)(1.0 / (N2 * a.psihat_t[i <= L ? i : N2 - i])));
+        }
+        __syncthreads();
+    }
+    lds_fft<T, MAXN>(buf, a.fn2, +1, a.tw_n2);
+    double2 *Fm = F + (int64_t)mi * a.nring;
+    for (int j = threadIdx.x; j <= L; j += fft_threads<T>(MAXN)) {
+        C v = buf[j];
+        double re = v.x, im = v.y;
+        if (j > 0) {
+            C u = buf[N2 - j];
+            re += sig * (double)u.x;
+            im += sig * (double)u.y;
+        }
+        const double wj = a.ring_w[j];
+        Fm[j] = make_double2(re * wj, im * wj);
+    }
+}
+
 // -------------------------------------------------------------- phi stage
 //
-// Long rows are split into two half-length transforms, each in a workgroup of
-// its own, so that twice as many transforms are in flight per CU (a 5880-point
-// FP64 row takes 94 KB of LDS, a whole CU's worth for one workgroup).  Both
-// directions split their output index, so the halves never write the same
-// element:
-//   synthesis, outputs k = 2 k' + h:  U[2 k' + h] = sum_m V_m e^{2 pi i m h / Np} e^{2 pi i m k' / nh},
-//     a half-length transform of the spectrum with m taken mod nh;
-//   adjoint, frequencies m = 2 m' + h:  V_m = sum_{k < nh} y_h[k] e^{-2 pi i m' k / nh},
-//     y_h[k] = (U[k] + (-1)^h U[k + nh]) e^{-2 pi i h k / Np}.
+// Long rows are split into S = 2 (or, above twice the LDS limit, 4) parts,
+// each a transform of length nh = Np / S in a workgroup of its own, so that
+// more transforms are in flight per CU (a 5880-point FP64 row takes 94 KB of
+// LDS, a whole CU's worth for one workgroup).  Both directions split their
+// output index, so the parts never write the same element:
+//   synthesis, outputs k = S k' + h:  U[S k' + h] = sum_m V_m e^{2 pi i m h / Np} e^{2 pi i m k' / nh},
+//     a transform of the spectrum with m taken mod nh (for S = 2 every m lands
+//     on its own entry, |m| <= mmax < nh / 2; for S = 4 the entries sum the
+//     orders that fold onto them);
+//   adjoint, frequencies m = S m' + h:  V_m = sum_{k < nh} y_h[k] e^{-2 pi i m' k / nh},
+//     y_h[k] = e^{-2 pi i h k / Np} sum_{j < S} U[k + j nh] e^{-2 pi i h j / S}.
 
-// Row and half of block b.  With split rows the two halves of a row go to
-// blocks 16 q + x and 16 q + 8 + x, which the round-robin dealing of blocks
-// places on the same XCD, so their interleaved outputs meet in one L2.
-__device__ inline void phi_block(int b, bool split, int &r, int &h) {
-    if (!split) {
+// Row and part of block b.  The S parts of a row go to blocks 8 (S q + h) + x,
+// which the round-robin dealing of blocks places on the same XCD, so their
+// interleaved outputs meet in one L2.
+__device__ inline void phi_block(int b, int parts, int &r, int &h) {
+    if (parts == 1) {
         r = b;
         h = 0;
         return;
     }
     const int x = b & 7, q = b >> 3;
-    h = q & 1;
-    r = 8 * (q >> 1) + x;
+    h = q % parts;
+    r = 8 * (q / parts) + x;
 }
 
-static inline unsigned phi_grid(int rows, bool split) { return split ? 16u * (unsigned)((rows + 7) / 8) : (unsigned)rows; }
+static inline unsigned phi_grid(int rows, int parts) {
+    return parts == 1 ? (unsigned)rows : 8u * (unsigned)parts * (unsigned)((rows + 7) / 8);
+}
 
 template <typename T, int MAXN>
 __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_phi_synth(StageArgs a, const typename CT<T>::type *V,
@@ -387,29 +523,42 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_phi_synth(StageArgs a,
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
     int r, h;
-    phi_block(blockIdx.x, a.split, r, h);
+    phi_block(blockIdx.x, a.parts, r, h);
     if (r >= a.rows_used) return;
-    const int Np = a.Nphi, nh = a.split ? Np / 2 : Np, mm = a.mmax;
+    const int Np = a.Nphi, S = a.parts, nh = Np / S, mm = a.mmax;
     const C *Vr = V + (int64_t)r * (2 * mm + 1);
     C *Ur = U + (int64_t)r * Np;
     C z;
     z.x = z.y = (T)0;
-    for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) buf[k] = z;
-    __syncthreads();
-    // |m| <= mmax < nh / 2: the m taken mod nh land on distinct entries
-    for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads<T>(MAXN)) {
-        const int m = mi - mm;
-        C v = cscale(Vr[mi], (T)(1.0 / a.psihat_p[abs(m)]));
-        if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, +1));
-        buf[m < 0 ? m + nh : m] = v;
+    if (S <= 2) {
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) buf[k] = z;
+        __syncthreads();
+        // |m| <= mmax < nh / 2: the m taken mod nh land on distinct entries
+        for (int mi = threadIdx.x; mi <= 2 * mm; mi += fft_threads<T>(MAXN)) {
+            const int m = mi - mm;
+            C v = cscale(Vr[mi], (T)(1.0 / a.psihat_p[abs(m)]));
+            if (h) v = cmul(v, twiddle<C>(a.tw_np_full, m < 0 ? m + Np : m, +1));
+            buf[m < 0 ? m + nh : m] = v;
+        }
+    } else {
+        // entry t sums the orders m = t (mod nh) in [-mmax, mmax]
+        for (int t = threadIdx.x; t < nh; t += fft_threads<T>(MAXN)) {
+            C acc = z;
+            for (int m = t - nh * ((t + mm) / nh); m <= mm; m += nh) {
+                C v = cscale(Vr[m + mm], (T)(1.0 / a.psihat_p[abs(m)]));
+                if (h) {
+                    int e = (int)(((int64_t)m * h) % Np);
+                    if (e < 0) e += Np;
+                    v = cmul(v, twiddle<C>(a.tw_np_full, e, +1));
+                }
+                acc = cadd(acc, v);
+            }
+            buf[t] = acc;
+        }
     }
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnp, +1, a.tw_np);
-    if (a.split) {
-        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) Ur[2 * k + h] = buf[k];
-    } else {
-        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) Ur[k] = buf[k];
-    }
+    for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) Ur[S * k + h] = buf[k];
 }
 
 template <typename T, int MAXN>
@@ -419,27 +568,36 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_phi_adjoint(StageArgs 
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
     int r, h;
-    phi_block(blockIdx.x, a.split, r, h);
+    phi_block(blockIdx.x, a.parts, r, h);
     if (r >= a.rows_used) return;
-    const int Np = a.Nphi, nh = a.split ? Np / 2 : Np, mm = a.mmax;
+    const int Np = a.Nphi, S = a.parts, nh = Np / S, mm = a.mmax;
     C *Vr = V + (int64_t)r * (2 * mm + 1);
     const C *Ur = U + (int64_t)r * Np;
-    if (a.split) {
+    if (S == 1) {
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) buf[k] = Ur[k];
+    } else if (S == 2) {
         for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) {
             const C u0 = Ur[k], u1 = Ur[k + nh];
             buf[k] = h ? cmul(csub(u0, u1), twiddle<C>(a.tw_np_full, k, -1)) : cadd(u0, u1);
         }
     } else {
-        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) buf[k] = Ur[k];
+        for (int k = threadIdx.x; k < nh; k += fft_threads<T>(MAXN)) {
+            C acc = Ur[k];
+            for (int j = 1; j < S; ++j) {
+                const C u = Ur[k + j * nh];
+                acc = cadd(acc, h ? cmul(u, twiddle<C>(a.tw_np_full, (h * j * nh) % Np, -1)) : u);
+            }
+            buf[k] = h ? cmul(acc, twiddle<C>(a.tw_np_full, h * k, -1)) : acc;
+        }
     }
     __syncthreads();
     lds_fft<T, MAXN>(buf, a.fnp, -1, a.tw_np);
-    // frequencies of this half: m = mi - mmax with m = h (mod 2) when split
-    const int step = a.split ? 2 : 1, mi0 = a.split ? ((h + mm) & 1) : 0;
-    for (int mi = mi0 + step * (int)threadIdx.x; mi <= 2 * mm; mi += step * fft_threads<T>(MAXN)) {
+    // frequencies of this part: m = mi - mmax with m = h (mod S)
+    const int mi0 = ((h + mm) % S + S) % S;
+    for (int mi = mi0 + S * (int)threadIdx.x; mi <= 2 * mm; mi += S * fft_threads<T>(MAXN)) {
         const int m = mi - mm;
         const int f = m < 0 ? m + Np : m;
-        const C v = buf[a.split ? (f >> 1) : f];
+        const C v = buf[(f - h) / S];
         Vr[mi] = cscale(v, (T)(1.0 / a.psihat_p[abs(m)]));
     }
 }
@@ -451,10 +609,10 @@ static StageArgs stage_args(const psht_plan_s &p) {
     StageArgs a;
     a.fn2 = to_dev(p.fft_n2.f);
     a.fnt = to_dev(p.fft_nt.f);
-    a.fnp = to_dev(p.phi_split ? p.fft_np_half.f : p.fft_np.f);
+    a.fnp = to_dev(p.g.phi_parts > 1 ? p.fft_np_part.f : p.fft_np.f);
     a.tw_n2 = reinterpret_cast<const double2 *>(p.fft_n2.d_tw);
     a.tw_nt = reinterpret_cast<const double2 *>(p.fft_nt.d_tw);
-    a.tw_np = reinterpret_cast<const double2 *>(p.phi_split ? p.fft_np_half.d_tw : p.fft_np.d_tw);
+    a.tw_np = reinterpret_cast<const double2 *>(p.g.phi_parts > 1 ? p.fft_np_part.d_tw : p.fft_np.d_tw);
     a.tw_np_full = reinterpret_cast<const double2 *>(p.fft_np.d_tw);
     a.L = g.Lmax;
     a.N2 = g.N2;
@@ -465,7 +623,8 @@ static StageArgs stage_args(const psht_plan_s &p) {
     a.spin = g.spin;
     a.row_lo = g.row_lo;
     a.rows_used = g.rows_used;
-    a.split = p.phi_split;
+    a.parts = p.g.phi_parts;
+    a.tsplit = p.theta_split;
     a.ring_w = p.d_ring_w;
     a.ring_mmax = p.d_ring_mmax;
     a.psihat_t = p.d_psihat_t;
@@ -479,48 +638,63 @@ template <typename F> static hipError_t set_lds(F kern, size_t bytes) {
 }
 
 // Calls fn(std::integral_constant<int, MAXN>) for the smallest build size
-// MAXN >= n (n <= 8192).
+// MAXN >= n (n <= 10240).
 template <typename Fn> static void tier_dispatch(int n, Fn fn) {
     if (n <= 1024) fn(std::integral_constant<int, 1024>());
     else if (n <= 2048) fn(std::integral_constant<int, 2048>());
     else if (n <= 2560) fn(std::integral_constant<int, 2560>());
     else if (n <= 4096) fn(std::integral_constant<int, 4096>());
-    else fn(std::integral_constant<int, 8192>());
+    else if (n <= 8192) fn(std::integral_constant<int, 8192>());
+    else fn(std::integral_constant<int, 10240>());
 }
 
 template <typename T>
 static void theta_synth_t(const psht_plan_s &p, const StageArgs &a, const double2 *F, void *V, hipStream_t st) {
     typedef typename CT<T>::type C;
-    const size_t lds = (size_t)p.g.Ntheta * sizeof(C);
-    tier_dispatch(p.g.Ntheta, [&](auto M) {
+    const int n = p.theta_split ? p.g.N2 : p.g.Ntheta;
+    const size_t lds = (size_t)n * sizeof(C);
+    tier_dispatch(n, [&](auto M) {
         constexpr int MX = decltype(M)::value;
-        set_lds(k_theta_synth<T, MX>, lds);
-        hipLaunchKernelGGL((k_theta_synth<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)), lds, st,
-                           a, F, static_cast<C *>(V));
+        if (p.theta_split) {
+            set_lds(k_theta_synth_split<T, MX>, lds);
+            hipLaunchKernelGGL((k_theta_synth_split<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)),
+                               lds, st, a, F, static_cast<C *>(V));
+        } else {
+            set_lds(k_theta_synth<T, MX>, lds);
+            hipLaunchKernelGGL((k_theta_synth<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)), lds,
+                               st, a, F, static_cast<C *>(V));
+        }
     });
 }
 
 template <typename T>
 static void theta_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *V, double2 *F, hipStream_t st) {
     typedef typename CT<T>::type C;
-    const size_t lds = (size_t)p.g.Ntheta * sizeof(C);
-    tier_dispatch(p.g.Ntheta, [&](auto M) {
+    const int n = p.theta_split ? p.g.N2 : p.g.Ntheta;
+    const size_t lds = (size_t)n * sizeof(C);
+    tier_dispatch(n, [&](auto M) {
         constexpr int MX = decltype(M)::value;
-        set_lds(k_theta_adjoint<T, MX>, lds);
-        hipLaunchKernelGGL((k_theta_adjoint<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)), lds,
-                           st, a, static_cast<const C *>(V), F);
+        if (p.theta_split) {
+            set_lds(k_theta_adjoint_split<T, MX>, lds);
+            hipLaunchKernelGGL((k_theta_adjoint_split<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)),
+                               dim3(fft_threads<T>(MX)), lds, st, a, static_cast<const C *>(V), F);
+        } else {
+            set_lds(k_theta_adjoint<T, MX>, lds);
+            hipLaunchKernelGGL((k_theta_adjoint<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)),
+                               lds, st, a, static_cast<const C *>(V), F);
+        }
     });
 }
 
 template <typename T>
 static void phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V, void *U, hipStream_t st) {
     typedef typename CT<T>::type C;
-    const int nh = p.phi_split ? p.g.Nphi / 2 : p.g.Nphi;
+    const int nh = p.g.Nphi / p.g.phi_parts;
     const size_t lds = (size_t)nh * sizeof(C);
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_phi_synth<T, MX>, lds);
-        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads<T>(MX)), lds,
+        hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(phi_grid(p.g.rows_used, p.g.phi_parts)), dim3(fft_threads<T>(MX)), lds,
                            st, a,
                            static_cast<const C *>(V), static_cast<C *>(U));
     });
@@ -529,12 +703,12 @@ static void phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V,
 template <typename T>
 static void phi_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *U, void *V, hipStream_t st) {
     typedef typename CT<T>::type C;
-    const int nh = p.phi_split ? p.g.Nphi / 2 : p.g.Nphi;
+    const int nh = p.g.Nphi / p.g.phi_parts;
     const size_t lds = (size_t)nh * sizeof(C);
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         set_lds(k_phi_adjoint<T, MX>, lds);
-        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(phi_grid(p.g.rows_used, p.phi_split)), dim3(fft_threads<T>(MX)),
+        hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(phi_grid(p.g.rows_used, p.g.phi_parts)), dim3(fft_threads<T>(MX)),
                            lds, st, a,
                            static_cast<const C *>(U), static_cast<C *>(V));
     });

@@ -519,6 +519,7 @@ struct AdjArgs {
     int nitems;
     const double4 *st_mu;
     const int2 *st_k;
+    bool accumulate;  // ring groups: add into the (cleared) output instead of storing
 };
 
 // Rings [j0 + 64 r + lane] of order m: seeds (first segment) or the stored states.
@@ -699,7 +700,9 @@ __device__ void adj_seg_item(const AdjArgs &A, const AdjItem &it, int G, double4
                         val = x == 0 ? d : -d;
                         dst = a.alm_out + 2 * (a.nalm + kk) + (1 - x);
                     }
-                    *dst = (m == 0 && imag) ? 0.0 : val;
+                    val = (m == 0 && imag) ? 0.0 : val;
+                    if (A.accumulate) atomicAdd(dst, val);
+                    else *dst = val;
                 }
             }
             buf ^= 1;
@@ -1038,7 +1041,10 @@ hipError_t launch_leg_adj_states(const psht_plan_s &p, const StateItem *items, i
 static hipError_t leg_adjoint_seg(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st) {
     // orders above mmax have no ring: their outputs (the tail of g and of c) are zero
     const int64_t nalm = (int64_t)(p.g.lmax + 1) * (p.g.lmax + 2) / 2;
-    if (p.alm_tail < nalm) {
+    if (p.adj_accumulate) {
+        hipError_t e = launch_fill_zero(alm, (size_t)nalm * 2 * 16, st);
+        if (e != hipSuccess) return e;
+    } else if (p.alm_tail < nalm) {
         double2 *g = static_cast<double2 *>(alm);
         hipError_t e = launch_fill_zero(g + p.alm_tail, (size_t)(nalm - p.alm_tail) * 16, st);
         if (e == hipSuccess) e = launch_fill_zero(g + nalm + p.alm_tail, (size_t)(nalm - p.alm_tail) * 16, st);
@@ -1052,6 +1058,7 @@ static hipError_t leg_adjoint_seg(const psht_plan_s &p, const double *F, void *a
     A.nitems = p.n_adj_items;
     A.st_mu = reinterpret_cast<const double4 *>(p.d_adj_mu);
     A.st_k = reinterpret_cast<const int2 *>(p.d_adj_k);
+    A.accumulate = p.adj_accumulate;
     const int G = p.adj_waves;
     const size_t lds = sizeof(double) * 2 * G * kAdjRedDoubles;
     const dim3 grid(p.n_adj_items), block(64 * G);

@@ -3,6 +3,7 @@
 // kernel Fourier tables, and the Legendre recurrence tables.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -287,7 +288,7 @@ static double es_beta(int W) {
 }
 
 bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double theta_min, double eps,
-                      int precision, bool with_grid, Error &err, bool with_cutoffs) {
+                      int precision, bool with_grid, Error &err, bool with_cutoffs, const psht_plan_options *opts) {
     static const int odd_primes[] = {3, 5, 7, 11, 13};
     static const int grid_primes[] = {2, 3, 5, 7};
     if (lmax < 0 || spin < 0 || spin > lmax) {
@@ -325,7 +326,19 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
         g.theta_max = ts * (1.0 + g.eps_apo);
         Lf = lmax * ts / M_PI * (1.0 + g.eps_apo) * (1.0 + g.eps_apo);
     }
-    g.full_sky = (lmax == 0) || !(g.theta_max < M_PI) || !(Lf < lmax);
+    if (opts && (opts->full_sky != 0 && opts->full_sky != 1)) {
+        err = {PSHT_ERR_ARG, "full_sky must be 0 or 1"};
+        return false;
+    }
+    if (opts && opts->window != PSHT_WINDOW_ES) {
+        err = {PSHT_ERR_UNSUPPORTED, "window bell not available"};
+        return false;
+    }
+    if (opts && opts->cl) {
+        err = {PSHT_ERR_UNSUPPORTED, "spectrum-tuned Lmax not available"};
+        return false;
+    }
+    g.full_sky = (opts && opts->full_sky) || (lmax == 0) || !(g.theta_max < M_PI) || !(Lf < lmax);
     int L;
     if (g.full_sky) {
         // The patch is too large to gain anything: evaluate the map itself on the
@@ -388,7 +401,15 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
     while (g.Ntheta < 2 * g.W + 4) g.Ntheta += 2 * g.N2;
     int np = std::max(2 * (2 * g.mmax + 1), 2 * g.W + 4);
     if (np % 2) ++np;
-    while (!is_smooth(np, grid_primes, 4)) np += 2;
+    // Rows longer than the 2560-point tier run as two half-length transforms in
+    // workgroups of their own (twice the transforms in flight per CU), rows
+    // longer than twice the LDS limit as four (Nphi then a multiple of 4).
+    g.phi_parts = np > 2 * kFftMaxLds64 ? 4 : (np > 2560 ? 2 : 1);
+    if (const char *e = getenv("PSHT_PHI_PARTS")) {  // tests and tuning runs: 1, 2 or 4 parts
+        const int v = atoi(e);
+        if ((v == 1 && np <= kFftMaxLds64) || v == 2 || v == 4) g.phi_parts = v;
+    }
+    while (!is_smooth(np, grid_primes, 4) || np % g.phi_parts) np += 2;
     g.Nphi = np;
     g.sx = g.Ntheta / (2.0 * g.theta_max);
     g.sy = g.Nphi / (2.0 * M_PI);

@@ -41,6 +41,7 @@ struct Geometry {
     int W = 0;
     double beta = 0, sigma = 2.0;
     int Ntheta = 0, Nphi = 0;
+    int phi_parts = 1;  // phi transforms as phi_parts transforms of Nphi / phi_parts points (1, 2 or 4)
     int row_lo = 0, rows_used = 0;
     double sx = 0, sy = 0;           // grid coordinate = theta*sx (rows), phi*sy (cols)
     std::vector<double> psihat_theta; // n = 0..Lmax
@@ -60,7 +61,8 @@ struct Geometry {
 constexpr double kPolarTauRel = 1e-4;
 
 bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double theta_min,
-                      double eps, int precision, bool with_grid, Error &err, bool with_cutoffs = true);
+                      double eps, int precision, bool with_grid, Error &err, bool with_cutoffs = true,
+                      const psht_plan_options *opts = nullptr);
 
 // Factorization of an FFT length into radices 4, 2, 3, 5, 7, 11, 13.
 struct FftFactors {
@@ -96,9 +98,10 @@ struct LegItem {
 };
 
 // Work item of the segmented Legendre adjoint: one workgroup of `waves`
-// wavefronts computes the outputs l in [la, lb) of order m from every active
-// ring of m.  Wave w holds the 64 R consecutive rings from jb + 64 R w, R per
-// lane.  An item that does not start at the seed l0 = max(m, s) starts from the
+// wavefronts computes the outputs l in [la, lb) of order m from the active
+// rings [jb, je) of m (every ring of m, or one ring group of an order with
+// more rings than an item holds).  Wave w holds the 64 R consecutive rings
+// from jb + 64 R w, R per lane.  An item that does not start at the seed l0 = max(m, s) starts from the
 // recurrence state stored at plan time for l = la (index soff of the item's
 // first ring; -1 for the first segment).  R = 0: the order has no active ring
 // and its outputs are zero.
@@ -143,6 +146,7 @@ struct psht_plan_s {
     int n_adj_items = 0;
     int adj_waves = 1;
     int adj_rmax = 6;  // largest rings per lane of any item (selects the kernel instantiation)
+    bool adj_accumulate = false;  // ring groups: items add into a cleared output instead of storing
     int adj_seg = 0;
     double *d_adj_mu = nullptr;    // [state] {mu+_l, mu+_{l-1}, mu-_l, mu-_{l-1}}
     int32_t *d_adj_k = nullptr;    // [state] {k+, k-}
@@ -155,8 +159,8 @@ struct psht_plan_s {
     double *d_psihat_t = nullptr, *d_psihat_p = nullptr;
     double *d_es_poly = nullptr;
     float *d_es_poly32 = nullptr;
-    psht::FftTable fft_n2, fft_nt, fft_np, fft_np_half;
-    bool phi_split = false;
+    psht::FftTable fft_n2, fft_nt, fft_np, fft_np_part;
+    bool theta_split = false;  // Theta grid transform as two N2-point transforms (NT = 2 N2 above the LDS limit)
     // points, sorted by tile
     int tile_x = 16, tile_y = 32, ntx = 0, nty = 0, ntiles = 0;
     double *d_px = nullptr, *d_py = nullptr;
@@ -234,8 +238,8 @@ TileGeom tile_geom(const psht_plan_s &p);
 // this many rings); 0 leaves the choice to the plan.
 int leg_rings_per_lane();
 
-// Largest FFT length one workgroup transforms in LDS.
-constexpr int kFftMaxLds64 = 8192;
-constexpr int kFftMaxLds32 = 8192;
+// Largest FFT length one workgroup transforms in LDS (160 KB on gfx950).
+constexpr int kFftMaxLds64 = 10240;
+constexpr int kFftMaxLds32 = 10240;
 
 }  // namespace psht

@@ -31,14 +31,29 @@ def _device_f64(x, device) -> torch.Tensor:
     return t.contiguous()
 
 
+def _options(full_sky: bool, window: str, cl):
+    """psht_plan_options (and the array it points to, kept alive by the caller)."""
+    opts = _lib.PlanOptions()
+    opts.full_sky = 1 if full_sky else 0
+    opts.window = _lib.WINDOWS[window]
+    arr = None
+    if cl is not None:
+        arr = np.ascontiguousarray(cl, dtype=np.float64)
+        opts.cl = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        opts.cl_lmax = int(arr.shape[0]) - 1
+    return opts, arr
+
+
 class Plan:
     """Plan for spin-`spin` synthesis / adjoint at the points (theta, phi)
     (patch frame: patch centre at the north pole), band limit `lmax`, target
     accuracy `epsilon`; precision "auto" (FP32 grid when epsilon >= 1e-6),
-    "fp32" or "fp64"."""
+    "fp32" or "fp64".  Options: `full_sky` (Fourier-sphere transform over the
+    whole sphere), `window` ("es" or "kb" apodization bell), `cl` (power
+    spectrum C_l, l = 0..lmax or more, to tune Lmax by the predicted error)."""
 
     def __init__(self, theta, phi, lmax: int, spin: int, epsilon: float, precision: str = "auto", device=None,
-                 stream=None):
+                 stream=None, full_sky: bool = False, window: str = "es", cl=None):
         lib = _lib.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         th = _device_f64(theta, self.device)
@@ -48,9 +63,10 @@ class Plan:
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = _stream(stream)
-            _lib.check(lib.psht_plan_create(ctypes.byref(handle), int(lmax), int(spin), int(th.shape[0]),
-                                            th.data_ptr() or None, ph.data_ptr() or None, float(epsilon),
-                                            _lib.PREC[precision], st))
+            opts, _keep = _options(full_sky, window, cl)
+            _lib.check(lib.psht_plan_create_ex(ctypes.byref(handle), int(lmax), int(spin), int(th.shape[0]),
+                                               th.data_ptr() or None, ph.data_ptr() or None, float(epsilon),
+                                               _lib.PREC[precision], ctypes.byref(opts), st))
         self._h = handle
         info = _lib.PlanInfo()
         _lib.check(lib.psht_plan_query(self._h, ctypes.byref(info)))
@@ -212,20 +228,22 @@ def adjoint(fmap, theta, phi, lmax, spin, epsilon, precision="auto"):
         p.close()
 
 
-def plan_geometry(lmax: int, spin: int, theta_star: float, epsilon: float, precision: str = "auto"):
+def plan_geometry(lmax: int, spin: int, theta_star: float, epsilon: float, precision: str = "auto",
+                  full_sky: bool = False, window: str = "es", cl=None):
     """Host-only plan parameters for a cap of radius theta_star: (info, ring_theta, ring_w, ring_mmax)."""
     lib = _lib.load()
     info = _lib.PlanInfo()
-    _lib.check(lib.psht_plan_geometry(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(info),
-                                      None, None, None, 0))
+    opts, _keep = _options(full_sky, window, cl)
+    _lib.check(lib.psht_plan_geometry_ex(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(opts),
+                                         ctypes.byref(info), None, None, None, 0))
     n = info.Lmax + 1
     th = np.zeros(n)
     w = np.zeros(n)
     mm = np.zeros(n, dtype=np.int32)
     dp = ctypes.POINTER(ctypes.c_double)
-    _lib.check(lib.psht_plan_geometry(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(info),
-                                      th.ctypes.data_as(dp), w.ctypes.data_as(dp),
-                                      mm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n))
+    _lib.check(lib.psht_plan_geometry_ex(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(opts),
+                                         ctypes.byref(info), th.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                         mm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n))
     return info.as_dict(), th, w, mm
 
 

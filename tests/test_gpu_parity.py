@@ -43,10 +43,11 @@ def alm_rel(a, b, lmax):
 
 # ------------------------------------------------------------------ FFT (P13)
 
-# the lengths cover every radix pass, the tiers of the LDS kernel up to 8192
-# points and the phi-row lengths of the lmax 2048 workload (5880 and its half)
+# the lengths cover every radix pass, the tiers of the LDS kernel up to 10240
+# points (the 160 KB of LDS a gfx950 workgroup may use) and the phi-row lengths
+# of the lmax 2048 workload (5880 and its half)
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 10, 12, 13, 14, 15, 91, 105, 143, 210, 1155, 2310, 2352, 2940, 4050, 5880,
-                               6000, 8192, 7 * 11 * 13 * 4])
+                               6000, 8192, 7 * 11 * 13 * 4, 8281, 9009, 10240])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_fft_vs_numpy(n, fp32):
     say("fft n=%d fp32=%s" % (n, fp32))
@@ -331,4 +332,29 @@ def test_adjoint_segments_vs_oracle(lmax, radius_deg, spin):
     assert np.all(at[:, l < spin] == 0)
     assert np.all(at[:, m == 0].imag == 0)
     assert plan.dropped_points() == 0
+    plan.close()
+
+
+@pytest.mark.parametrize("spin,prec,eps", [(2, "fp64", 1e-10), (0, "fp32", 1e-5)])
+def test_adjoint_ring_groups_vs_oracle(spin, prec, eps, monkeypatch):
+    """Orders cut into ring groups (forced here at 100 rings; plans with more
+    rings than an item holds, full sky above lmax ~ 3000, need them): the
+    items add into the cleared output.  Against the oracle, over a
+    junk-filled output buffer."""
+    monkeypatch.setenv("PSHT_ADJ_GROUP", "100")
+    lmax = 512
+    th, ph = syn.uniform_cap(30000, 30 * DEG, 9960 + spin)
+    plan = Plan(th, ph, lmax, spin, eps, prec)
+    assert plan.info["Lmax"] + 1 > 100
+    idx = np.sort(syn.rng(9970).choice(th.shape[0], 400, replace=False))
+    g = np.zeros(th.shape[0], dtype=np.complex64 if plan.info["map_is_fp32"] else np.complex128)
+    g[idx] = syn.gaussian_map(400, 9971 + spin)
+    junk = torch.full((2, syn.nalm(lmax)), complex(float("nan"), 1e300), dtype=torch.complex128, device="cuda")
+    at = plan.adjoint(dev(g), out=junk).cpu().numpy()
+    ref = oracle.adjoint(g[idx].astype(np.complex128), th[idx], ph[idx], lmax, spin)
+    err = alm_rel(at, ref, lmax)
+    say("ring groups spin %d %s: rel L2 %.3e" % (spin, prec, err))
+    assert err <= 10 * eps
+    m, l = syn.alm_m_l(lmax)
+    assert np.all(at[:, l < spin] == 0) and np.all(at[:, m == 0].imag == 0)
     plan.close()
