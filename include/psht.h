@@ -103,6 +103,13 @@ typedef struct {
      * for the segment starts. */
     int32_t adj_segment, adj_waves, adj_rings_per_lane;
     int64_t adj_states;
+    /* Lmax_rule: Lmax from eq. Lmax2; Lmax differs from it when the plan was
+     * tuned to a power spectrum (psht_plan_options.cl), and predicted_error is
+     * then the predicted relative error of the band-limited weighted map for
+     * fields of that spectrum (Sec. II.D, eq. st); -1 when not tuned. */
+    int32_t Lmax_rule;
+    double predicted_error;
+    int32_t window;     /* PSHT_WINDOW_* of the plan */
 } psht_plan_info;
 
 /* Options of psht_plan_create_ex / psht_plan_geometry_ex (NULL: all defaults,
@@ -113,21 +120,34 @@ typedef struct {
  *              without the partial-sky steps of Sec. II); exact up to the
  *              NUFFT error for any point set.  0: partial sky (the mode falls
  *              back to the full sky only when the patch is too large to gain).
- *   window   : apodization bell of Sec. II.C: PSHT_WINDOW_ES (0, the
- *              exponential-of-semicircle bell) or PSHT_WINDOW_KB (1, the
- *              Kaiser-Bessel bell).
- *   cl, cl_lmax : optional host array cl[0..cl_lmax] (cl_lmax >= lmax), the
- *              power spectrum C_l of the fields to be transformed; when given,
- *              Lmax is the smallest smooth value whose predicted isotropic
- *              error (Sec. II.D) stays below epsilon, instead of eq. Lmax2.
- *              NULL / 0: eq. Lmax2. */
+ *   window   : apodization bell of Sec. II.C, all three with shape parameter
+ *              alpha = |ln epsilon| / pi: PSHT_WINDOW_ES (0, the
+ *              exponential-of-semicircle bell of eq. KB), PSHT_WINDOW_KB (1,
+ *              the Kaiser-Bessel bell I0(pi alpha sqrt(1 - x^2)), whose Fourier
+ *              transform is the closed form given with eq. KB) or
+ *              PSHT_WINDOW_PSWF (2, the order-0 prolate spheroidal (Slepian)
+ *              function of bandwidth c = pi alpha).
+ *   cl, cl_lmax : optional host array cl[0..cl_lmax] (cl_lmax >= lmax,
+ *              finite, >= 0), the power spectrum C_l of the fields to be
+ *              transformed (C^E_l + C^B_l for spin > 0); read during the call
+ *              only.  When given, Lmax is the smallest smooth value, at most
+ *              the rule's, whose predicted relative error of the weighted
+ *              band-limited map for such fields (Sec. II.D, eqs. s2m, st, cm,
+ *              cms) is at most epsilon / 2; theta_max and the window are the
+ *              rule's.  NULL: the rule's Lmax.  Ignored in full-sky mode.
+ *   lmax_rule : PSHT_LMAX_RULE_BAND (0): theta_max and Lmax from eq. Lmax2
+ *              (the smallest band limit); PSHT_LMAX_RULE_COST (1): the
+ *              apodization length that minimizes the Legendre work of the
+ *              rings with polar optimization (footnote to eq. Lmax2). */
 typedef struct {
     int32_t full_sky;
     int32_t window;
     const double *cl;
     int32_t cl_lmax;
+    int32_t lmax_rule;
 } psht_plan_options;
-enum { PSHT_WINDOW_ES = 0, PSHT_WINDOW_KB = 1 };
+enum { PSHT_WINDOW_ES = 0, PSHT_WINDOW_KB = 1, PSHT_WINDOW_PSWF = 2 };
+enum { PSHT_LMAX_RULE_BAND = 0, PSHT_LMAX_RULE_COST = 1 };
 
 /* Build a plan for npoints points (device arrays theta, phi; read during the
  * call only, not kept).  Validates lmax >= 0, 0 <= spin <= lmax,
@@ -200,6 +220,15 @@ psht_status psht_synth_noalloc(psht_plan plan, int nmaps, const void *alm, void 
 /* Free the plan's device memory.  The caller must synchronise every stream
  * that still runs work of this plan first.  NULL is a no-op. */
 void psht_plan_destroy(psht_plan plan);
+
+/* Great-circle spectrum of an isotropic spin-s field with power spectrum
+ * C_l (Sec. II.D, eq. cm; eq. cms with C_l = C^E_l + C^B_l for s > 0):
+ *   c_m = sum_{l >= max(|m|, s)} C_l (2l+1)/2 |d^l_{m,-s}(pi/2)|^2,
+ * so that the field along a great circle through the poles has the
+ * one-dimensional correlation (1/2pi) sum_m c_m e^{i m (theta - theta')}.
+ * cl: host array cl[0..lmax]; cm: host array of 2 lmax + 1 doubles receiving
+ * c_m at cm[m + lmax], m = -lmax..lmax (host computation, long double). */
+psht_status psht_great_circle_spectrum(int lmax, int spin, const double *cl, double *cm);
 
 /* Thread-local text for the last non-OK status of this thread ("" if none). */
 const char *psht_last_error(void);

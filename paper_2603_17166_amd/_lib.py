@@ -30,7 +30,7 @@ EXPORTS = (
     "psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_destroy",
     "psht_last_error", "psht_plan_geometry", "psht_stage", "psht_fft", "psht_legendre_column",
     "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc",
-    "psht_plan_check", "psht_plan_create_ex", "psht_plan_geometry_ex",
+    "psht_plan_check", "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum",
 )
 
 STAGE_NAMES = ("leg_synth", "theta_synth", "phi_synth", "interp", "grid_zero", "spread", "phi_adj", "theta_adj",
@@ -50,19 +50,21 @@ class PlanInfo(ctypes.Structure):
         ("npoints", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t), ("workspace_bytes_per_map", ctypes.c_size_t),
         ("kernel_poly_err", ctypes.c_double),
         ("adj_segment", ctypes.c_int32), ("adj_waves", ctypes.c_int32), ("adj_rings_per_lane", ctypes.c_int32),
-        ("adj_states", ctypes.c_int64),
+        ("adj_states", ctypes.c_int64), ("Lmax_rule", ctypes.c_int32), ("predicted_error", ctypes.c_double),
+        ("window", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-WINDOWS = {"es": 0, "kb": 1}
+WINDOWS = {"es": 0, "kb": 1, "pswf": 2}
+LMAX_RULES = {"band": 0, "cost": 1}
 
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("full_sky", ctypes.c_int32), ("window", ctypes.c_int32), ("cl", ctypes.POINTER(ctypes.c_double)),
-                ("cl_lmax", ctypes.c_int32)]
+                ("cl_lmax", ctypes.c_int32), ("lmax_rule", ctypes.c_int32)]
 
 
 class PshtError(RuntimeError):
@@ -90,6 +92,7 @@ def load() -> ctypes.CDLL:
     lib.psht_plan_geometry_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                           ctypes.POINTER(PlanOptions), ctypes.POINTER(PlanInfo), dp, dp, i32p,
                                           ctypes.c_int]
+    lib.psht_great_circle_spectrum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
     lib.psht_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.psht_synth.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
@@ -111,7 +114,7 @@ def load() -> ctypes.CDLL:
     for name in ("psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_geometry",
                  "psht_stage", "psht_fft", "psht_legendre_column", "psht_plan_set_timing", "psht_plan_timing",
                  "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc", "psht_plan_check",
-                 "psht_plan_create_ex", "psht_plan_geometry_ex"):
+                 "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -130,6 +130,9 @@ void fill_info(const psht_plan_s &p, psht_plan_info *info) {
     info->adj_waves = p.adj_waves;
     info->adj_rings_per_lane = p.adj_rmax;
     info->adj_states = p.n_adj_states;
+    info->Lmax_rule = g.Lmax_rule;
+    info->predicted_error = g.predicted_error;
+    info->window = g.window;
 }
 
 struct ScopedDevFree {
@@ -698,6 +701,18 @@ psht_status psht_plan_timing(psht_plan plan, double *ms, int64_t *launches) {
 }
 
 const char *psht_last_error(void) { return g_last_error.c_str(); }
+
+psht_status psht_great_circle_spectrum(int lmax, int spin, const double *cl, double *cm) {
+    if (lmax < 0 || spin < 0 || spin > lmax || !cl || !cm) return fail(PSHT_ERR_ARG, "bad arguments");
+    try {
+        std::vector<double> v;
+        psht::great_circle_spectrum(lmax, spin, cl, v);
+        std::copy(v.begin(), v.end(), cm);
+        return PSHT_OK;
+    } catch (...) {
+        return fail(PSHT_ERR_NOMEM, "host allocation failed");
+    }
+}
 
 psht_status psht_plan_check(psht_plan plan, int64_t *dropped, void *hip_stream) {
     if (!plan || !dropped) return fail(PSHT_ERR_ARG, "plan or dropped is NULL");

@@ -76,37 +76,143 @@ struct GL {
 
 // ------------------------------------------------------------------ window
 
-// w(Theta): 1 on |Theta| <= Theta*, then 1 - CDF of the exponential-of-
-// semicircle bell b(u) ~ exp(alpha pi (sqrt(1 - (2u/dT)^2) - 1)), |u| <= dT/2,
-// dT = pi - Theta*, i.e. the convolution of a top-hat of support 2 pi - dT
-// with the unit-area bell (Sec. II.C, eq. KB and Fig. 4).  The bell CDF is
-// integrated after u = (dT/2) sin t, which removes the square-root endpoint.
+// Bells of the apodization window (Sec. II.C), as functions of x in [-1, 1]
+// (x = 2u / dT across the bell's support dT):
+//   ES   (eq. KB):     exp(alpha pi (sqrt(1 - x^2) - 1));
+//   KB   (Kaiser-Bessel): I0(alpha pi sqrt(1 - x^2)) e^{-alpha pi}, whose Fourier
+//        transform over the support is the closed form printed with eq. KB;
+//   PSWF (Slepian): the order-0 prolate spheroidal wave function psi_0(c, x)
+//        with bandwidth c = alpha pi, the function of support [-1, 1] whose
+//        Fourier transform is most concentrated on |k| <= alpha.
+// All three are even and positive on (-1, 1); the window uses their unit-area
+// cumulative integral.
+
+// I0(z), z >= 0, by its power series sum_k (z^2/4)^k / (k!)^2 (all terms
+// positive; z <= 40 here, so about 60 terms reach long-double precision).
+static ld bessel_i0(ld z) {
+    const ld q = z * z / 4;
+    ld term = 1, sum = 1;
+    for (int k = 1; k < 400; ++k) {
+        term *= q / ((ld)k * k);
+        sum += term;
+        if (term < sum * 1e-21L) break;
+    }
+    return sum;
+}
+
+// psi_0(c, x) = sum_{k even} b_k Pn_k(x), Pn_k = sqrt(k + 1/2) P_k, from the
+// Legendre-basis form of the prolate differential operator
+//   L psi = -((1 - x^2) psi')' + c^2 x^2 psi = chi psi:
+// in the orthonormal basis Pn_k it is symmetric tridiagonal over k of one
+// parity, with diagonal k(k+1) + c^2 (2k^2 + 2k - 1) / ((2k - 1)(2k + 3)) and
+// off-diagonal c^2 (k+1)(k+2) / ((2k+3) sqrt((2k+1)(2k+5))) between k and
+// k + 2 (from x^2 P_k in P_{k-2}, P_k, P_{k+2}).  psi_0 belongs to the smallest
+// eigenvalue chi_0 in (0, c^2/3]: chi_0 by Sturm-count bisection, the vector
+// by inverse iteration at a shift just below chi_0.  Coefficients fall off
+// faster than geometrically for k beyond c, so k <= 2 c + 80 is ample.
+static std::vector<ld> pswf0_coeffs(ld c) {
+    const int n = (int)(c + 41);  // k = 0, 2, ..., 2 (n - 1)
+    std::vector<ld> d(n), e(n, 0);
+    const ld c2 = c * c;
+    for (int i = 0; i < n; ++i) {
+        const ld k = 2 * i;
+        d[i] = k * (k + 1) + c2 * (2 * k * k + 2 * k - 1) / ((2 * k - 1) * (2 * k + 3));
+        e[i] = c2 * (k + 1) * (k + 2) / ((2 * k + 3) * sqrtl((2 * k + 1) * (2 * k + 5)));
+    }
+    auto below = [&](ld lam) {  // eigenvalues < lam = negative pivots of A - lam I
+        int cnt = 0;
+        ld q = d[0] - lam;
+        if (q < 0) ++cnt;
+        for (int i = 1; i < n; ++i) {
+            if (q == 0) q = 1e-300L;
+            q = d[i] - lam - e[i - 1] * e[i - 1] / q;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    ld lo = 0, hi = c2 / 3 + 1;
+    for (int it = 0; it < 200; ++it) {
+        const ld mid = (lo + hi) / 2;
+        if (below(mid) >= 1) hi = mid;
+        else lo = mid;
+    }
+    const ld shift = lo - 1e-9L * (1 + lo);
+    std::vector<ld> b(n, 1), cp(n), dp(n);
+    for (int it = 0; it < 4; ++it) {  // solve (A - shift) y = b by the Thomas algorithm
+        ld den = d[0] - shift;
+        cp[0] = e[0] / den;
+        dp[0] = b[0] / den;
+        for (int i = 1; i < n; ++i) {
+            den = d[i] - shift - e[i - 1] * cp[i - 1];
+            cp[i] = e[i] / den;
+            dp[i] = (b[i] - e[i - 1] * dp[i - 1]) / den;
+        }
+        b[n - 1] = dp[n - 1];
+        for (int i = n - 2; i >= 0; --i) b[i] = dp[i] - cp[i] * b[i + 1];
+        ld nrm = 0;
+        for (ld v : b) nrm += v * v;
+        nrm = sqrtl(nrm);
+        for (ld &v : b) v /= nrm;
+    }
+    // sign: psi_0(0) > 0, with P_k(0) = (-1)^(k/2) (k-1)!!/k!!
+    ld p0 = 0, pk = 1;
+    for (int i = 0; i < n; ++i) {
+        const ld k = 2 * i;
+        if (i > 0) pk *= -(k - 1) / k;
+        p0 += b[i] * sqrtl(k + 0.5L) * pk;
+    }
+    if (p0 < 0)
+        for (ld &v : b) v = -v;
+    return b;
+}
+
+// w(Theta): 1 on |Theta| <= Theta*, 0 at Theta = pi, and in between 1 - the
+// unit-area cumulative integral of the bell over a support dT = pi - Theta*
+// centred at h = (pi + Theta*)/2: the convolution of a top-hat of support
+// 2 pi - dT with the bell (Sec. II.C, Fig. 4).  ES and KB cumulative integrals
+// are taken by Gauss-Legendre quadrature after x = sin t (which removes the
+// square-root endpoint); the PSWF one term by term from
+// int_{-1}^{x} P_k = (P_{k+1}(x) - P_{k-1}(x)) / (2k + 1), k >= 1.
 struct Window {
     ld Theta_star, alpha, dT, h, norm;
+    int kind;
     const GL *gl;
-    Window(ld Ts, ld a, const GL *g) : Theta_star(Ts), alpha(a), gl(g) {
+    std::vector<ld> pc;
+    Window(ld Ts, ld a, const GL *g, int bell = PSHT_WINDOW_ES) : Theta_star(Ts), alpha(a), kind(bell), gl(g) {
         dT = kPiL - Ts;
         h = (kPiL + Ts) / 2;
-        norm = cdf_t(kPiL / 2);
+        if (kind == PSHT_WINDOW_PSWF) pc = pswf0_coeffs(alpha * kPiL);
+        norm = cdf(1);
     }
-    // integral of exp(alpha pi (cos t - 1)) cos t over [-pi/2, tv]
-    ld cdf_t(ld tv) const {
-        ld a = -kPiL / 2, half = (tv - a) / 2, s = 0;
-        for (size_t i = 0; i < gl->x.size(); ++i) {
-            ld t = a + half * (gl->x[i] + 1);
-            s += gl->w[i] * expl(alpha * kPiL * (cosl(t) - 1)) * cosl(t);
+    ld bell_t(ld t) const {  // bell at x = sin t, times dx/dt = cos t
+        const ld ct = cosl(t);
+        if (kind == PSHT_WINDOW_KB) return bessel_i0(alpha * kPiL * ct) * expl(-alpha * kPiL) * ct;
+        return expl(alpha * kPiL * (ct - 1)) * ct;
+    }
+    // integral of the bell over [-1, x]
+    ld cdf(ld x) const {
+        if (x > 1) x = 1;
+        if (x < -1) x = -1;
+        if (kind == PSHT_WINDOW_PSWF) {
+            ld pm = 1, p = x, s = pc[0] * sqrtl(0.5L) * (x + 1);  // P_0, P_1
+            for (int k = 1; k < 2 * (int)pc.size(); ++k) {
+                const ld pn = ((2 * k + 1) * x * p - k * pm) / (k + 1);  // P_{k+1}
+                if ((k & 1) == 0) s += pc[k / 2] * sqrtl(k + 0.5L) * (pn - pm) / (2 * k + 1);
+                pm = p;
+                p = pn;
+            }
+            return s;
         }
+        const ld a = -kPiL / 2, half = (asinl(x) - a) / 2;
+        ld s = 0;
+        for (size_t i = 0; i < gl->x.size(); ++i) s += gl->w[i] * bell_t(a + half * (gl->x[i] + 1));
         return s * half;
     }
     double operator()(ld Theta) const {
         ld T = fabsl(Theta);
         if (T <= Theta_star) return 1.0;
         if (T >= kPiL) return 0.0;
-        ld v = T - h;  // in [-dT/2, dT/2]
-        ld arg = 2 * v / dT;
-        if (arg > 1) arg = 1;
-        if (arg < -1) arg = -1;
-        return (double)(1 - cdf_t(asinl(arg)) / norm);
+        return (double)(1 - cdf(2 * (T - h) / dT) / norm);
     }
 };
 
@@ -272,6 +378,125 @@ static int ring_cutoff(int lmax, int s, ld theta, ld tau) {
     return lo;
 }
 
+// ------------------------------------------- error predictor (Sec. II.D)
+
+// Great-circle spectrum of an isotropic field with power spectrum C_l
+// (eq. cm, and eq. cms for spin s with C_l = C^E_l + C^B_l):
+//   c_m = sum_{l >= max(|m|, s)} C_l (2l+1)/2 |d^l_{m,-s}(pi/2)|^2,  m = -lmax..lmax,
+// with d^l_{-m,-s} = d^l_{m,s} for the negative orders.  (2l+1)/2 d^2 = 2 pi lambda^2
+// for the normalized lambda = sqrt((2l+1)/4 pi) d, computed by the three-term
+// recurrence in l at theta = pi/2 (cos theta = 0) from the single-term seed,
+// in long double.  cm[m + lmax].
+void great_circle_spectrum(int lmax, int s, const double *cl, std::vector<double> &cm) {
+    cm.assign(2 * (size_t)lmax + 1, 0.0);
+    const ld S = s, half = 0.5L;
+    for (int m = 0; m <= lmax; ++m) {
+        const int l0 = std::max(m, s);
+        if (l0 > lmax) continue;
+        const ld M = m;
+        const ld lnK = 0.5L * logl((2 * l0 + 1) / (4 * kPiL)) +
+                       0.5L * (lgammal(2 * l0 + 1) - lgammal(m + s + 1) - lgammal(2 * l0 - m - s + 1));
+        // cos(pi/4) = sin(pi/4) = 2^-1/2: both seeds are K 2^{-(|m-s| + m + s)/2}
+        const ld seed = expl(lnK - half * (std::abs(m - s) + m + s) * logl(2.0L));
+        ld lp = seed, lm = seed, lpp = 0, lmp = 0;
+        ld sp = 0, sm = 0;
+        for (int l = l0; l <= lmax; ++l) {
+            sp += (ld)cl[l] * lp * lp;
+            sm += (ld)cl[l] * lm * lm;
+            if (l == lmax) break;
+            const ld L = l;
+            const ld D = sqrtl(((L + 1) * (L + 1) - M * M) * ((L + 1) * (L + 1) - S * S));
+            const ld a = sqrtl((2 * L + 3) * (2 * L + 1)) * (L + 1) / D;
+            const ld b = (m * s == 0) ? 0 : a * M * S / (L * (L + 1));
+            const ld c = (l == l0) ? 0
+                                   : sqrtl((2 * L + 3) / (2 * L - 1)) * (L + 1) *
+                                         sqrtl((L * L - M * M) * (L * L - S * S)) / (L * D);
+            const ld np = b * lp - c * lpp, nm = -b * lm - c * lmp;  // (a x +/- b), x = cos(pi/2) = 0
+            lpp = lp;
+            lp = np;
+            lmp = lm;
+            lm = nm;
+        }
+        cm[lmax + m] = (double)(2 * kPiL * sp);
+        if (m > 0) cm[lmax - m] = (double)(2 * kPiL * sm);
+    }
+}
+
+// Predicted relative error of the weighted, band-limited map (Sec. II.D): for
+// the rings Theta_j = 2 pi j / N2, j = -L..L, of this L, with weights w_j and
+// theta_j = Theta_j theta_max / pi, the error on the wave e^{i m theta} is
+//   sigma_m(theta) = | sum_j w_j D_j(Theta) e^{i m theta_j} - e^{i m theta} |
+// (eq. s2m, D the Dirichlet kernel of eq. Dnz), and a field with great-circle
+// spectrum c_m has sigma^2(theta) = (1/2pi) sum_m c_m sigma_m^2(theta)
+// (eq. st).  Returned: max over theta <= theta* of sigma(theta) / <|f|^2>^(1/2),
+// <|f|^2> = (1/2pi) sum_m c_m.  theta is sampled on 33 equidistant points of
+// [0, theta*] and half-way between consecutive rings in the last fifth of the
+// cap (where the error peaks, between the nodes); the orders with a stride of
+// at most lmax / 512 (each sampled order standing for `stride` orders).
+template <typename WinFn>
+double predicted_error(int lmax, double theta_star, double theta_max, int L, const WinFn &win,
+                       const std::vector<double> &cm) {
+    const int N2 = 2 * L + 1;
+    const double h = 2.0 * theta_max / N2;  // ring spacing in theta
+    std::vector<double> thj(N2), wj(N2), Thj(N2);
+    for (int k = 0; k < N2; ++k) {
+        const int j = k - L;
+        Thj[k] = 2.0 * M_PI * j / N2;
+        thj[k] = j * h;
+        wj[k] = win(std::fabs(Thj[k]));
+    }
+    std::vector<double> ths;
+    for (int k = 0; k <= 32; ++k) ths.push_back(theta_star * k / 32.0);
+    for (int j = 0; j < L; ++j) {
+        const double mid = (j + 0.5) * h;
+        if (mid >= 0.8 * theta_star && mid <= theta_star) ths.push_back(mid);
+    }
+    const int stride = std::max(1, lmax / 512);
+    std::vector<int> ms;
+    for (int m = -lmax; m <= lmax; m += stride) ms.push_back(m);
+    if (ms.back() != lmax) ms.push_back(lmax);
+    double total = 0.0;
+    for (int m : ms) total += cm[m + lmax];
+    if (!(total > 0)) return 0.0;
+    std::vector<double> worst(ths.size(), 0.0);
+    auto eval = [&](size_t it) {
+        const double th = ths[it], Th = th * M_PI / theta_max;
+        std::vector<double> ar(N2);
+        for (int k = 0; k < N2; ++k) {
+            const double d = Th - Thj[k], sd = std::sin(0.5 * d);
+            const double D = std::fabs(sd) < 1e-15 ? 1.0 : std::sin(0.5 * N2 * d) / (N2 * sd);
+            ar[k] = wj[k] * D;
+        }
+        double acc = 0.0;
+        for (int m : ms) {
+            // sum_k a_k e^{i m theta_k}, theta_k = (k - L) h: phasor rotated step by step
+            const double cr = std::cos(m * h), ci = std::sin(m * h);
+            double pr = std::cos(-m * h * L), pi = std::sin(-m * h * L);
+            double sr = 0, si = 0;
+            for (int k = 0; k < N2; ++k) {
+                sr += ar[k] * pr;
+                si += ar[k] * pi;
+                const double t = pr * cr - pi * ci;
+                pi = pr * ci + pi * cr;
+                pr = t;
+            }
+            const double er = sr - std::cos(m * th), ei = si - std::sin(m * th);
+            acc += cm[m + lmax] * (er * er + ei * ei);
+        }
+        worst[it] = acc;
+    };
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nt; ++t)
+        pool.emplace_back([&, t]() {
+            for (size_t it = t; it < ths.size(); it += nt) eval(it);
+        });
+    for (auto &x : pool) x.join();
+    double mx = 0.0;
+    for (double v : worst) mx = std::max(mx, v);
+    return std::sqrt(mx / total);
+}
+
 // ---------------------------------------------------------------- geometry
 
 static int es_width(double eps) {
@@ -330,14 +555,55 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
         err = {PSHT_ERR_ARG, "full_sky must be 0 or 1"};
         return false;
     }
-    if (opts && opts->window != PSHT_WINDOW_ES) {
-        err = {PSHT_ERR_UNSUPPORTED, "window bell not available"};
+    if (opts && (opts->window < PSHT_WINDOW_ES || opts->window > PSHT_WINDOW_PSWF)) {
+        err = {PSHT_ERR_ARG, "unknown window bell"};
         return false;
     }
-    if (opts && opts->cl) {
-        err = {PSHT_ERR_UNSUPPORTED, "spectrum-tuned Lmax not available"};
+    if (opts && (opts->lmax_rule != PSHT_LMAX_RULE_BAND && opts->lmax_rule != PSHT_LMAX_RULE_COST)) {
+        err = {PSHT_ERR_ARG, "unknown Lmax rule"};
         return false;
     }
+    g.window = opts ? opts->window : PSHT_WINDOW_ES;
+    // Sec. II.C, footnote to eq. Lmax2: instead of the smallest Lmax, the
+    // apodization length that minimizes the Legendre work with polar
+    // optimization.  With Delta l = 2 alpha the band estimate of eq. Lmax for a
+    // fractional apodization length x is Lmax(x) = lmax theta*/pi (1 + x)(1 + c/x),
+    // c = 2 |ln eps| / (theta* lmax) (its minimum x = sqrt(c) is eq. Lmax2), and
+    // the work of the Lmax + 1 rings is sum_j m_j (lmax + 1 - m_j / 2) with
+    // m_j = min(lmax, lmax sin theta_j) (the pairs (m, l), m <= m_j, l >= m).
+    // x is scanned over [sqrt(c)/4, 2 sqrt(c)] with Lmax rounded to a smooth N2.
+    if (opts && opts->lmax_rule == PSHT_LMAX_RULE_COST && lmax > 0 && Lf < lmax && g.theta_max < M_PI) {
+        const double c = 2.0 * ln_eps / (ts * lmax), x0 = std::sqrt(c);
+        double best = HUGE_VAL, bx = g.eps_apo;
+        for (int i = 0; i <= 400; ++i) {
+            const double x = x0 * (0.25 + 1.75 * i / 400.0), tm = ts * (1 + x);
+            if (!(tm < M_PI)) break;
+            int Lc = std::max(1, (int)std::ceil(lmax * ts / M_PI * (1 + x) * (1 + c / x) - 1e-9));
+            while (!is_smooth(2 * Lc + 1, odd_primes, 5)) ++Lc;
+            double work = 0;
+            for (int j = 0; j <= Lc; ++j) {
+                const double mj = std::min((double)lmax, lmax * std::sin(2.0 * M_PI * j / (2 * Lc + 1) * tm / M_PI));
+                work += mj * (lmax + 1 - 0.5 * mj);
+            }
+            if (work < best) {
+                best = work;
+                bx = x;
+            }
+        }
+        g.eps_apo = bx;
+        g.theta_max = ts * (1.0 + bx);
+        Lf = lmax * ts / M_PI * (1.0 + bx) * (1.0 + c / bx);
+    }
+    if (opts && opts->cl && opts->cl_lmax < lmax) {
+        err = {PSHT_ERR_ARG, "cl must hold C_l for l = 0..lmax (cl_lmax >= lmax)"};
+        return false;
+    }
+    if (opts && opts->cl)
+        for (int l = 0; l <= lmax; ++l)
+            if (!(opts->cl[l] >= 0.0) || !std::isfinite(opts->cl[l])) {
+                err = {PSHT_ERR_ARG, "cl must be finite and non-negative"};
+                return false;
+            }
     g.full_sky = (opts && opts->full_sky) || (lmax == 0) || !(g.theta_max < M_PI) || !(Lf < lmax);
     int L;
     if (g.full_sky) {
@@ -350,14 +616,38 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
         L = std::max(1, (int)std::ceil(Lf - 1e-9));
     }
     while (!is_smooth(2 * L + 1, odd_primes, 5)) ++L;
-    g.Lmax = L;
-    g.N2 = 2 * L + 1;
-    g.nring = L + 1;
+    g.Lmax_rule = L;
 
     // Rings Theta_j = 2 pi j / N2 (j = 0..Lmax), theta_j = Theta_j theta_max / pi.
     GL gl_win(160);
     ld Theta_star = g.full_sky ? kPiL : kPiL * (ld)ts / (ld)g.theta_max;
-    Window win(Theta_star, (ld)g.alpha, &gl_win);
+    Window win(Theta_star, (ld)g.alpha, &gl_win, g.window);
+
+    // Lmax from the predicted error for the caller's spectrum (Sec. II.D): the
+    // smallest smooth L <= the eq. Lmax2 value whose predicted relative error
+    // stays below epsilon / 2 (the NUFFT takes the other part of the budget),
+    // found by bisection over the smooth values (the error falls as L grows).
+    g.predicted_error = -1.0;
+    if (opts && opts->cl && !g.full_sky) {
+        std::vector<double> cm;
+        great_circle_spectrum(lmax, spin, opts->cl, cm);
+        auto wfun = [&](double T) { return win((ld)T); };
+        std::vector<int> cand;
+        for (int c = 1; c <= L; ++c)
+            if (is_smooth(2 * c + 1, odd_primes, 5)) cand.push_back(c);
+        int lo = 0, hi = (int)cand.size() - 1;  // cand[hi] = L meets the target by construction of the rule
+        const double target = 0.5 * eps;
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (predicted_error(lmax, ts, g.theta_max, cand[mid], wfun, cm) <= target) hi = mid;
+            else lo = mid + 1;
+        }
+        L = cand[hi];
+        g.predicted_error = predicted_error(lmax, ts, g.theta_max, L, wfun, cm);
+    }
+    g.Lmax = L;
+    g.N2 = 2 * L + 1;
+    g.nring = L + 1;
     g.ring_theta.resize(g.nring);
     g.ring_w.resize(g.nring);
     for (int j = 0; j < g.nring; ++j) {

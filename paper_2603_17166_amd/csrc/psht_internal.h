@@ -55,7 +55,14 @@ struct Geometry {
     double es_poly_err = 0;
     double predicted_speedup = 0;
     double legendre_triples = 0;
+    int window = PSHT_WINDOW_ES;   // apodization bell
+    int Lmax_rule = 0;             // Lmax from eq. Lmax2 (before any spectrum tuning)
+    double predicted_error = -1;   // predicted relative error for the caller's C_l (Sec. II.D); -1: not tuned
 };
+
+// Great-circle spectrum c_m, m = -lmax..lmax, of an isotropic field with power
+// spectrum cl[0..lmax] (Sec. II.D, eq. cm / eq. cms); cm[m + lmax].
+void great_circle_spectrum(int lmax, int spin, const double *cl, std::vector<double> &cm);
 
 // m cut-off threshold relative to epsilon.
 constexpr double kPolarTauRel = 1e-4;

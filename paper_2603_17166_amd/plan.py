@@ -31,11 +31,12 @@ def _device_f64(x, device) -> torch.Tensor:
     return t.contiguous()
 
 
-def _options(full_sky: bool, window: str, cl):
+def _options(full_sky: bool, window: str, cl, lmax_rule: str = "band"):
     """psht_plan_options (and the array it points to, kept alive by the caller)."""
     opts = _lib.PlanOptions()
     opts.full_sky = 1 if full_sky else 0
     opts.window = _lib.WINDOWS[window]
+    opts.lmax_rule = _lib.LMAX_RULES[lmax_rule]
     arr = None
     if cl is not None:
         arr = np.ascontiguousarray(cl, dtype=np.float64)
@@ -49,11 +50,12 @@ class Plan:
     (patch frame: patch centre at the north pole), band limit `lmax`, target
     accuracy `epsilon`; precision "auto" (FP32 grid when epsilon >= 1e-6),
     "fp32" or "fp64".  Options: `full_sky` (Fourier-sphere transform over the
-    whole sphere), `window` ("es" or "kb" apodization bell), `cl` (power
-    spectrum C_l, l = 0..lmax or more, to tune Lmax by the predicted error)."""
+    whole sphere), `window` ("es", "kb" or "pswf" apodization bell), `cl` (power
+    spectrum C_l, l = 0..lmax or more, to tune Lmax by the predicted error),
+    `lmax_rule` ("band": eq. Lmax2; "cost": least Legendre work)."""
 
     def __init__(self, theta, phi, lmax: int, spin: int, epsilon: float, precision: str = "auto", device=None,
-                 stream=None, full_sky: bool = False, window: str = "es", cl=None):
+                 stream=None, full_sky: bool = False, window: str = "es", cl=None, lmax_rule: str = "band"):
         lib = _lib.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         th = _device_f64(theta, self.device)
@@ -63,7 +65,7 @@ class Plan:
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = _stream(stream)
-            opts, _keep = _options(full_sky, window, cl)
+            opts, _keep = _options(full_sky, window, cl, lmax_rule)
             _lib.check(lib.psht_plan_create_ex(ctypes.byref(handle), int(lmax), int(spin), int(th.shape[0]),
                                                th.data_ptr() or None, ph.data_ptr() or None, float(epsilon),
                                                _lib.PREC[precision], ctypes.byref(opts), st))
@@ -229,11 +231,11 @@ def adjoint(fmap, theta, phi, lmax, spin, epsilon, precision="auto"):
 
 
 def plan_geometry(lmax: int, spin: int, theta_star: float, epsilon: float, precision: str = "auto",
-                  full_sky: bool = False, window: str = "es", cl=None):
+                  full_sky: bool = False, window: str = "es", cl=None, lmax_rule: str = "band"):
     """Host-only plan parameters for a cap of radius theta_star: (info, ring_theta, ring_w, ring_mmax)."""
     lib = _lib.load()
     info = _lib.PlanInfo()
-    opts, _keep = _options(full_sky, window, cl)
+    opts, _keep = _options(full_sky, window, cl, lmax_rule)
     _lib.check(lib.psht_plan_geometry_ex(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(opts),
                                          ctypes.byref(info), None, None, None, 0))
     n = info.Lmax + 1
@@ -265,4 +267,13 @@ def fft(x: torch.Tensor, sign: int) -> torch.Tensor:
     batch = x.numel() // n if n else 0
     _lib.check(_lib.load().psht_fft(n, batch, sign, 1 if fp32 else 0, x.data_ptr(), out.data_ptr(),
                                     _stream()))
+    return out
+
+
+def great_circle_spectrum(lmax: int, spin: int, cl) -> np.ndarray:
+    """c_m, m = -lmax..lmax (index m + lmax), of an isotropic spin-`spin` field with power spectrum cl[0..lmax]."""
+    c = np.ascontiguousarray(cl, dtype=np.float64)
+    out = np.zeros(2 * lmax + 1)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.check(_lib.load().psht_great_circle_spectrum(lmax, spin, c.ctypes.data_as(dp), out.ctypes.data_as(dp)))
     return out

@@ -1,6 +1,7 @@
 """CPU tests of the library's host side: the C ABI exports, the kernels'
 own Legendre seeds/tables (evaluated on the host), the plan parameter rules
 (Table I, the error model of eq. s2m), the window and the polar cut-offs."""
+import ctypes
 import math
 import os
 import re
@@ -10,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2603_17166_amd import _lib
-from paper_2603_17166_amd.plan import legendre_column, plan_geometry
+from paper_2603_17166_amd.plan import great_circle_spectrum, legendre_column, plan_geometry
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 DEG = math.pi / 180
@@ -201,3 +202,159 @@ def test_kernel_polynomial_table_accuracy(eps, prec):
     bound = max(1e-3 * eps, 2e-7 if info["map_is_fp32"] else 1e-14)
     assert bool(info["map_is_fp32"]) == (prec == "auto" and eps >= 1e-6)
     assert 0.0 < info["kernel_poly_err"] <= bound
+
+
+@pytest.mark.parametrize("lmax,s", [(64, 0), (64, 2), (300, 2), (200, 3), (40, 1)])
+def test_great_circle_spectrum_vs_oracle(lmax, s):
+    """c_m of eq. cm / eq. cms from the library's long-double recurrence at
+    theta = pi/2 against the oracle's Wigner d at pi/2, for a non-trivial
+    spectrum; negative m uses d^l_{|m|, s}."""
+    l = np.arange(lmax + 1)
+    cl = np.exp(-0.3 * np.sqrt(l)) * (1 + 0.5 * np.cos(l))
+    cm = great_circle_spectrum(lmax, s, cl)
+    ref = np.zeros(2 * lmax + 1)
+    for m in range(-lmax, lmax + 1):
+        d = oracle.wigner_d(lmax, m, -s, math.pi / 2)
+        ref[m + lmax] = np.sum(cl * (2 * l + 1) / 2 * d ** 2)
+    assert np.max(np.abs(cm - ref)) <= 1e-13 * np.max(ref)
+
+
+def test_great_circle_spectrum_closed_forms():
+    """Sum rule: sum_m |d^l_{m,-s}|^2 = 1 (unitarity), so sum_m c_m =
+    sum_l C_l (2l+1)/2.  Single multipole l = L at spin 0: c_0 =
+    (2L+1)/2 P_L(0)^2 with P_L(0) = (-1)^(L/2) (L-1)!!/L!! for even L and 0
+    for odd L; and c_m = c_-m."""
+    lmax = 120
+    l = np.arange(lmax + 1)
+    for s in (0, 2, 5):
+        cl = (l >= s) / (1.0 + l) ** 1.5
+        cm = great_circle_spectrum(lmax, s, cl)
+        assert abs(cm.sum() / np.sum(cl * (2 * l + 1) / 2) - 1) < 1e-13
+    for L in (10, 11, 64, 97):
+        cl = np.zeros(lmax + 1)
+        cl[L] = 1.0
+        cm = great_circle_spectrum(lmax, 0, cl)
+        p0 = 0.0 if L % 2 else (-1) ** (L // 2) * math.exp(math.lgamma(L + 1) - L * math.log(2) - 2 * math.lgamma(L // 2 + 1))
+        assert abs(cm[lmax] - (2 * L + 1) / 2 * p0 ** 2) < 1e-13
+        assert np.allclose(cm, cm[::-1], rtol=0, atol=1e-14)
+        assert np.all(cm[: lmax - L] == 0) and np.all(cm[lmax + L + 1:] == 0)
+
+
+@pytest.mark.parametrize("lmax,ts,eps,s", [(512, 5, 1e-5, 2), (512, 3, 1e-8, 0), (1024, 3, 1e-10, 0)])
+def test_tuned_lmax_predicted_error_vs_brute_force(lmax, ts, eps, s):
+    """Lmax tuned to a red spectrum C_l = (l+1)^-2 (Sec. II.D): it is at most
+    the eq. Lmax2 value, and the field error of eq. st, evaluated by brute
+    force (eq. s2m over every m = -lmax..lmax on a fine theta grid with the
+    plan's rings and weights), stays below epsilon / 2 of the field's rms and
+    agrees with the plan's own (subsampled) prediction."""
+    l = np.arange(lmax + 1)
+    cl = 1.0 / (1.0 + l) ** 2
+    info, th, w, _ = plan_geometry(lmax, s, ts * DEG, eps, cl=cl)
+    base = plan_geometry(lmax, s, ts * DEG, eps)[0]
+    assert base["predicted_error"] == -1.0 and base["Lmax"] == base["Lmax_rule"]
+    assert info["Lmax_rule"] == base["Lmax"] and info["Lmax"] < info["Lmax_rule"]
+    assert info["theta_max"] == base["theta_max"]
+    cm = great_circle_spectrum(lmax, s, cl)
+    ms = np.arange(-lmax, lmax + 1)
+    sig = _sigma_m(info, th, w, lmax, ntheta=800, ms=ms)
+    brute = math.sqrt(np.max(sig ** 2 @ cm) / cm.sum())
+    assert brute <= 0.6 * eps
+    assert 0.7 < info["predicted_error"] / brute < 1.3
+
+
+def test_tuning_arguments():
+    for cl in (np.ones(50), -np.ones(129), np.full(129, np.nan)):
+        with pytest.raises(_lib.PshtError) as e:
+            plan_geometry(128, 0, 0.2, 1e-8, cl=cl)
+        assert e.value.code == _lib.PSHT_ERR_ARG
+    # full-sky plans keep Lmax = lmax whatever the spectrum
+    info = plan_geometry(128, 0, 0.2, 1e-8, full_sky=True, cl=np.ones(129))[0]
+    assert info["Lmax"] >= 128 and info["predicted_error"] == -1.0
+
+
+def _scipy_bell(kind, alpha, x):
+    """The three bells of Sec. II.C on [-1, 1] from scipy's special functions."""
+    import scipy.special as sp
+    if kind == "es":
+        return np.exp(alpha * math.pi * (np.sqrt(1 - x * x) - 1))
+    if kind == "kb":
+        return sp.i0(alpha * math.pi * np.sqrt(1 - x * x))
+    return sp.pro_ang1(0, 0, alpha * math.pi, x)[0]
+
+
+def test_kaiser_bessel_bell_fourier_closed_form():
+    """The Kaiser-Bessel bell I0(pi alpha sqrt(1 - (Theta/pi)^2)) on
+    [-pi, pi] has the normalized Fourier transform printed with eq. KB:
+    (pi alpha / sinh(pi alpha)) sinh(pi sqrt(alpha^2 - k^2)) / (pi sqrt(alpha^2 - k^2))
+    (sin for k > alpha), checked by quadrature."""
+    import scipy.integrate as si
+    alpha = abs(math.log(1e-8)) / math.pi
+    b0 = si.quad(lambda t: _scipy_bell("kb", alpha, t / math.pi), -math.pi, math.pi, epsrel=1e-13)[0]
+    for k in (0.0, 1.5, 4.0, alpha - 0.3, alpha + 0.7, 9.0):
+        got = si.quad(lambda t: _scipy_bell("kb", alpha, t / math.pi) * math.cos(k * t), -math.pi, math.pi,
+                      epsrel=1e-12, epsabs=1e-14 * b0, limit=400)[0] / b0
+        q = alpha * alpha - k * k
+        shape = (math.sinh(math.pi * math.sqrt(q)) / (math.pi * math.sqrt(q)) if q > 0 else
+                 (math.sin(math.pi * math.sqrt(-q)) / (math.pi * math.sqrt(-q)) if q < 0 else 1.0))
+        want = math.pi * alpha / math.sinh(math.pi * alpha) * shape
+        assert abs(got - want) < 1e-11
+
+
+@pytest.mark.parametrize("kind", ["es", "kb", "pswf"])
+@pytest.mark.parametrize("lmax,ts,eps", [(512, 10, 1e-5), (1024, 20, 1e-10)])
+def test_window_bells_vs_scipy(kind, lmax, ts, eps):
+    """Ring weights = 1 - the unit-area cumulative integral of the chosen bell
+    across the apodization zone (Sec. II.C, Fig. 4), against scipy's bells
+    integrated by adaptive quadrature."""
+    import scipy.integrate as si
+    info, th, w, _ = plan_geometry(lmax, 0, ts * DEG, eps, window=kind)
+    assert info["window"] == _lib.WINDOWS[kind]
+    a = info["alpha"]
+    Ts = math.pi / (1 + info["eps_apo"])
+    dT, h = math.pi - Ts, (math.pi + Ts) / 2
+    Th = th * math.pi / info["theta_max"]
+
+    def integral(x):
+        return si.quad(lambda y: _scipy_bell(kind, a, y), -1, x, epsabs=0, epsrel=1e-13, limit=200)[0]
+
+    norm = integral(1.0)
+    for T, wj in zip(Th, w):
+        ref = 1.0 if T <= Ts else 1.0 - integral(min(2 * (T - h) / dT, 1.0)) / norm
+        assert abs(wj - ref) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["kb", "pswf"])
+@pytest.mark.parametrize("lmax,ts,eps", [(512, 10, 1e-5), (512, 20, 1e-10), (2048, 35.5, 1e-7)])
+def test_error_model_s2m_other_bells(kind, lmax, ts, eps):
+    """Eq. s2m by brute force for the Kaiser-Bessel and Slepian windows (same
+    alpha, apodization length and Lmax as the ES rule): every wave is
+    reproduced inside the cap to epsilon."""
+    info, th, w, _ = plan_geometry(lmax, 0, ts * DEG, eps, window=kind)
+    ms = np.arange(lmax + 1) if lmax <= 512 else np.unique(np.concatenate([np.arange(0, lmax + 1, 7), np.arange(lmax - 64, lmax + 1)]))
+    assert np.max(_sigma_m(info, th, w, lmax, ms=ms)) <= eps
+
+
+@pytest.mark.parametrize("lmax,ts,eps", [(512, 10, 1e-5), (1024, 20, 1e-10), (2048, 35.3, 1e-7)])
+def test_cost_lmax_rule(lmax, ts, eps):
+    """The least-work rule (footnote to eq. Lmax2) shortens the apodization
+    zone, does no more Legendre work than eq. Lmax2, and keeps the eq. s2m
+    error below epsilon."""
+    band = plan_geometry(lmax, 2, ts * DEG, eps)[0]
+    info, th, w, _ = plan_geometry(lmax, 2, ts * DEG, eps, lmax_rule="cost")
+    assert info["eps_apo"] < band["eps_apo"] and info["theta_max"] < band["theta_max"]
+    assert info["legendre_triples"] <= band["legendre_triples"]
+    ms = np.unique(np.concatenate([np.arange(0, lmax + 1, 5), np.arange(lmax - 64, lmax + 1)]))
+    assert np.max(_sigma_m(info, th, w, lmax, ms=ms)) <= eps
+
+
+def test_option_arguments():
+    for kw in ({"window": "es"}, ):
+        plan_geometry(128, 0, 0.2, 1e-8, **kw)
+    opts = _lib.PlanOptions()
+    info = _lib.PlanInfo()
+    lib = _lib.load()
+    for field, bad in (("window", 3), ("lmax_rule", 2), ("full_sky", 2)):
+        opts = _lib.PlanOptions()
+        setattr(opts, field, bad)
+        st = lib.psht_plan_geometry_ex(128, 0, 0.2, 1e-8, 0, ctypes.byref(opts), ctypes.byref(info), None, None, None, 0)
+        assert st == _lib.PSHT_ERR_ARG
