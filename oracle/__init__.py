@@ -121,3 +121,70 @@ def alm_dot(a: np.ndarray, b: np.ndarray, lmax: int) -> float:
 def map_dot(f: np.ndarray, g: np.ndarray) -> float:
     """Real inner product on maps: sum_p Re(conj(f_p) g_p)."""
     return float(np.sum((np.conj(f) * g).real))
+
+
+# ---------------------------------------------------------------- rotations
+#
+# Patch frame (Sec. II, step 1: coordinates in which the patch centre is the
+# north pole).  A rotation R = Rz(alpha) Ry(beta) Rz(gamma) (active, z-y-z
+# Euler angles) acts on points as n -> R n and on a field as f -> f o R^-1.
+# With the Wigner functions D^l_{m m'}(alpha, beta, gamma) =
+# exp(-i m alpha) d^l_{m m'}(beta) exp(-i m' gamma) (d from wigner_d above) the
+# coefficients of the rotated field are a'_lm = sum_{m'} D^l_{m m'} a_lm',
+# a_{l,-m'} = (-1)^m' conj(a_lm') for fields that obey the reality condition;
+# g and c of a spin field each rotate this way.
+
+
+def rotation_matrix(alpha: float, beta: float, gamma: float) -> np.ndarray:
+    """3x3 matrix of Rz(alpha) Ry(beta) Rz(gamma)."""
+    def rz(a):
+        c, s = np.cos(a), np.sin(a)
+        return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+    def ry(b):
+        c, s = np.cos(b), np.sin(b)
+        return np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+
+    return rz(alpha) @ ry(beta) @ rz(gamma)
+
+
+def rotate_alm(alm: np.ndarray, lmax: int, alpha: float, beta: float, gamma: float) -> np.ndarray:
+    """a'_lm = sum_{m'=-l..l} exp(-i m alpha) d^l_{m m'}(beta) exp(-i m' gamma) a_lm'
+    for each row of alm (shape (ncomp, nalm), m >= 0 stored); O(lmax^3)."""
+    alm = np.atleast_2d(np.asarray(alm, dtype=np.complex128))
+    out = np.zeros_like(alm)
+    l = np.arange(lmax + 1)
+    for m in range(lmax + 1):
+        acc = np.zeros((alm.shape[0], lmax + 1), dtype=np.complex128)
+        for mp in range(-lmax, lmax + 1):
+            d = wigner_d(lmax, m, mp, beta)
+            k = abs(mp)
+            lsel = l[max(m, k):]
+            a = alm[:, alm_index(lmax, lsel, k)]
+            if mp < 0:
+                a = (-1) ** k * np.conj(a)
+            if k == 0:
+                a = a.real + 0j
+            acc[:, lsel] += d[lsel] * np.exp(-1j * mp * gamma) * a
+        lsel = l[m:]
+        out[:, alm_index(lmax, lsel, m)] = np.exp(-1j * m * alpha) * acc[:, lsel]
+    return out
+
+
+def rotate_points(theta: np.ndarray, phi: np.ndarray, alpha: float, beta: float, gamma: float):
+    """(theta', phi', psi) of the points R n, phi' in [0, 2 pi).  psi is the
+    angle from the rotated local basis vector R e_theta(n) to e_theta(R n),
+    measured towards e_phi(R n)."""
+    R = rotation_matrix(alpha, beta, gamma)
+    th = np.asarray(theta, dtype=np.float64)
+    ph = np.asarray(phi, dtype=np.float64)
+    n = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    et = np.stack([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)])
+    n2 = R @ n
+    et_rot = R @ et
+    th2 = np.arctan2(np.hypot(n2[0], n2[1]), n2[2])
+    ph2 = np.mod(np.arctan2(n2[1], n2[0]), 2 * np.pi)
+    et2 = np.stack([np.cos(th2) * np.cos(ph2), np.cos(th2) * np.sin(ph2), -np.sin(th2)])
+    ep2 = np.stack([-np.sin(ph2), np.cos(ph2), np.zeros_like(ph2)])
+    psi = np.arctan2(np.sum(et_rot * ep2, axis=0), np.sum(et_rot * et2, axis=0))
+    return th2, ph2, psi

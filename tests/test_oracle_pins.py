@@ -246,3 +246,89 @@ def test_deep_polar_seeds_do_not_underflow():
     cosg = mpmath.cos(t1) * mpmath.cos(t2) + mpmath.sin(t1) * mpmath.sin(t2) * mpmath.cos(p1 - p2)
     want = -(2 * ell + 1) / (4 * mpmath.pi) * mpmath.legendre(ell, cosg)
     assert abs(f[0] - float(want)) < 1e-12 * abs(float(want))
+
+
+# --- Rotations into the patch frame (Sec. II step 1) -------------------------------------
+
+ANGLES = [(0.3, 1.1, -0.7), (2.0, 2.9, 0.4), (-1.2, 0.05, 3.0), (0.0, -2.61, -0.9)]
+
+
+def _scipy_matrix(alpha, beta, gamma):
+    from scipy.spatial.transform import Rotation
+    return Rotation.from_euler("ZYZ", [alpha, beta, gamma]).as_matrix()
+
+
+@pytest.mark.parametrize("ang", ANGLES)
+def test_rotation_matrix_and_points_vs_scipy(ang):
+    """Rz(alpha) Ry(beta) Rz(gamma) is scipy's intrinsic ZYZ rotation; rotated
+    points are R n."""
+    R = _scipy_matrix(*ang)
+    assert np.allclose(oracle.rotation_matrix(*ang), R, atol=1e-15)
+    th, ph = syn.uniform_cap(200, 3.0, 5)
+    th2, ph2, psi = oracle.rotate_points(th, ph, *ang)
+    n = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    n2 = np.stack([np.sin(th2) * np.cos(ph2), np.sin(th2) * np.sin(ph2), np.cos(th2)])
+    assert np.max(np.abs(R @ n - n2)) < 1e-14
+    assert np.all((ph2 >= 0) & (ph2 < 2 * PI)) and np.all(np.abs(psi) <= PI)
+
+
+def test_rotation_about_z_is_a_phase():
+    """beta = 0: a'_lm = exp(-i m (alpha + gamma)) a_lm; points move in phi
+    only and the local basis does not turn (psi = 0)."""
+    lmax, a, g = 20, 0.37, -1.3
+    alm = syn.gaussian_alm(lmax, 2, 21)
+    m, _ = syn.alm_m_l(lmax)
+    got = oracle.rotate_alm(alm, lmax, a, 0.0, g)
+    want = np.exp(-1j * m * (a + g)) * np.where(m == 0, alm.real + 0j, alm)
+    assert np.max(np.abs(got - want)) < 1e-14
+    th, ph = syn.uniform_cap(50, 2.0, 6)
+    th2, ph2, psi = oracle.rotate_points(th, ph, a, 0.0, g)
+    assert np.allclose(th2, th, atol=1e-14) and np.max(np.abs(psi)) < 1e-14
+    assert np.max(np.abs(np.angle(np.exp(1j * (ph2 - ph - a - g))))) < 1e-13
+
+
+@pytest.mark.parametrize("ang", ANGLES)
+def test_rotation_of_a_dipole_is_the_rotated_vector(ang):
+    """The l = 1 part of f(n) = v.n (a_10 = sqrt(4 pi/3) v_z,
+    a_11 = -sqrt(2 pi/3)(v_x - i v_y)) rotates into that of (R v).n, with R
+    from scipy."""
+    lmax = 3
+
+    def dipole(v):
+        a = np.zeros((2, oracle.nalm(lmax)), dtype=np.complex128)
+        a[0, oracle.alm_index(lmax, 1, 0)] = math.sqrt(4 * PI / 3) * v[2]
+        a[0, oracle.alm_index(lmax, 1, 1)] = -math.sqrt(2 * PI / 3) * (v[0] - 1j * v[1])
+        return a
+
+    v = np.array([0.3, -1.2, 0.7])
+    got = oracle.rotate_alm(dipole(v), lmax, *ang)
+    assert np.max(np.abs(got - dipole(_scipy_matrix(*ang) @ v))) < 1e-14
+
+
+@pytest.mark.parametrize("s", [0, 1, 2, 3])
+def test_rotation_through_synthesis(s):
+    """The field of the rotated coefficients at the rotated points is the
+    original field times exp(i s psi) (the spin-s basis turns by psi): ties
+    rotate_alm and rotate_points to the pinned synthesis."""
+    lmax = 24
+    alm = syn.gaussian_alm(lmax, s, 30 + s)
+    th, ph = syn.uniform_cap(60, 2.8, 31)
+    for ang in ANGLES:
+        f = oracle.synth(alm, th, ph, lmax, s)
+        th2, ph2, psi = oracle.rotate_points(th, ph, *ang)
+        f2 = oracle.synth(oracle.rotate_alm(alm, lmax, *ang), th2, ph2, lmax, s)
+        assert np.max(np.abs(f2 - np.exp(1j * s * psi) * f)) < 1e-13 * np.max(np.abs(f))
+
+
+def test_rotation_inverse_and_norm():
+    """R^-1 = Rz(-gamma) Ry(-beta) Rz(-alpha) undoes the rotation, and the
+    rotation keeps the coefficient norm (D is unitary)."""
+    lmax = 30
+    alm = syn.gaussian_alm(lmax, 0, 40)
+    m, _ = syn.alm_m_l(lmax)
+    alm = np.where(m == 0, alm.real + 0j, alm)
+    a, b, g = ANGLES[1]
+    r = oracle.rotate_alm(alm, lmax, a, b, g)
+    back = oracle.rotate_alm(r, lmax, -g, -b, -a)
+    assert np.max(np.abs(back - alm)) < 1e-13
+    assert abs(oracle.alm_dot(r, r, lmax) / oracle.alm_dot(alm, alm, lmax) - 1) < 1e-13
