@@ -230,6 +230,52 @@ void psht_plan_destroy(psht_plan plan);
  * c_m at cm[m + lmax], m = -lmax..lmax (host computation, long double). */
 psht_status psht_great_circle_spectrum(int lmax, int spin, const double *cl, double *cm);
 
+/* ---- Patch frame (Sec. II, step 1) -----------------------------------------
+ * The method works in coordinates in which the patch centre is the north
+ * pole.  These calls move coefficients, points and spin bases from another
+ * frame (e.g. equatorial) into that frame.  R = Rz(alpha) Ry(beta) Rz(gamma)
+ * is an active rotation with z-y-z Euler angles; for a patch centred at
+ * colatitude theta_c and longitude phi_c, (alpha, beta, gamma) =
+ * (psi_0, -theta_c, -phi_c) takes the centre to the pole (any psi_0 turns the
+ * patch about its centre).  With coefficients a' from psht_rotate_alm and
+ * points n' = R n from psht_rotate_points, the spin-s synthesis satisfies
+ *   f'(n') = exp(i s psi) f(n),
+ * psi being the angle psht_rotate_points returns; psht_spin_phase applies or
+ * removes that factor.  The adjoint of a rotation is the rotation by
+ * (-gamma, -beta, -alpha). */
+
+/* Workspace bytes psht_rotate_alm needs: ncomp (lmax + 1)(2 lmax + 1) * 16. */
+psht_status psht_rotate_alm_workspace(int lmax, int ncomp, size_t *bytes);
+
+/* a'_lm = exp(-i m alpha) sum_{m' = -l..l} d^l_{m m'}(beta) exp(-i m' gamma) a_lm'
+ * (Wigner D of Appendix A's d-matrix), with a_{l,-m'} = (-1)^m' conj(a_lm')
+ * (reality condition of Sec. I; the imaginary part of a_l0 is ignored), for
+ * each of ncomp (1 or 2: g and c of a spin field) coefficient sets.
+ * alm_in, alm_out: device complex128 [ncomp][nalm], m-major layout of
+ * psht_synth; they must not overlap.  0 <= lmax <= 16383; angles finite.
+ * workspace: device memory of at least psht_rotate_alm_workspace bytes,
+ * overwritten.  O(lmax^3) work on hip_stream; asynchronous.  The first call
+ * for a given lmax on a device builds a small log-factorial table there
+ * (kept until the process ends; one synchronous copy).  alm_out is
+ * accumulated with device-scope atomic adds, so it must be ordinary device
+ * memory. */
+psht_status psht_rotate_alm(int lmax, int ncomp, double alpha, double beta, double gamma, const void *alm_in,
+                            void *alm_out, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* n' = R n for npoints points: device double arrays theta, phi in, theta_out
+ * in [0, pi], phi_out in [0, 2 pi), psi_out in [-pi, pi] (the angle from R
+ * e_theta(n) to e_theta(n'), measured towards e_phi(n')).  Outputs may alias
+ * the inputs element for element.  Asynchronous on hip_stream. */
+psht_status psht_rotate_points(int64_t npoints, double alpha, double beta, double gamma, const double *theta,
+                               const double *phi, double *theta_out, double *phi_out, double *psi_out,
+                               void *hip_stream);
+
+/* map[i] *= exp(i sign spin psi[i]) in place; map complex64 (fp32 = 1) or
+ * complex128 (fp32 = 0) [npoints] on the device, psi double [npoints];
+ * sign +1 or -1.  Asynchronous on hip_stream. */
+psht_status psht_spin_phase(int64_t npoints, int spin, int sign, int fp32, const double *psi, void *map,
+                            void *hip_stream);
+
 /* Thread-local text for the last non-OK status of this thread ("" if none). */
 const char *psht_last_error(void);
 

@@ -31,6 +31,7 @@ EXPORTS = (
     "psht_last_error", "psht_plan_geometry", "psht_stage", "psht_fft", "psht_legendre_column",
     "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc",
     "psht_plan_check", "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum",
+    "psht_rotate_alm_workspace", "psht_rotate_alm", "psht_rotate_points", "psht_spin_phase",
 )
 
 STAGE_NAMES = ("leg_synth", "theta_synth", "phi_synth", "interp", "grid_zero", "spread", "phi_adj", "theta_adj",
@@ -102,6 +103,11 @@ def load() -> ctypes.CDLL:
     lib.psht_plan_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp]
     lib.psht_plan_destroy.argtypes = [vp]
     lib.psht_plan_destroy.restype = None
+    d = ctypes.c_double
+    lib.psht_rotate_alm_workspace.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    lib.psht_rotate_alm.argtypes = [ctypes.c_int, ctypes.c_int, d, d, d, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.psht_rotate_points.argtypes = [ctypes.c_int64, d, d, d, vp, vp, vp, vp, vp, vp]
+    lib.psht_spin_phase.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.psht_last_error.argtypes = []
     lib.psht_last_error.restype = ctypes.c_char_p
     lib.psht_plan_geometry.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -114,7 +120,8 @@ def load() -> ctypes.CDLL:
     for name in ("psht_plan_create", "psht_plan_query", "psht_synth", "psht_adjoint", "psht_plan_geometry",
                  "psht_stage", "psht_fft", "psht_legendre_column", "psht_plan_set_timing", "psht_plan_timing",
                  "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc", "psht_plan_check",
-                 "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum"):
+                 "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum",
+                 "psht_rotate_alm_workspace", "psht_rotate_alm", "psht_rotate_points", "psht_spin_phase"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <vector>
 #include <new>
 #include <string>
 
@@ -701,6 +702,93 @@ psht_status psht_plan_timing(psht_plan plan, double *ms, int64_t *launches) {
 }
 
 const char *psht_last_error(void) { return g_last_error.c_str(); }
+
+psht_status psht_rotate_alm_workspace(int lmax, int ncomp, size_t *bytes) {
+    if (lmax < 0 || lmax > 16383 || (ncomp != 1 && ncomp != 2) || !bytes)
+        return fail(PSHT_ERR_ARG, "need 0 <= lmax <= 16383, ncomp 1 or 2, bytes not NULL");
+    *bytes = (size_t)ncomp * (size_t)(lmax + 1) * (size_t)(2 * lmax + 1) * 16;
+    return PSHT_OK;
+}
+
+psht_status psht_rotate_alm(int lmax, int ncomp, double alpha, double beta, double gamma, const void *alm_in,
+                            void *alm_out, void *workspace, size_t ws_bytes, void *hip_stream) {
+    size_t need = 0;
+    if (psht_rotate_alm_workspace(lmax, ncomp, &need) != PSHT_OK) return PSHT_ERR_ARG;
+    if (!std::isfinite(alpha) || !std::isfinite(beta) || !std::isfinite(gamma))
+        return fail(PSHT_ERR_ARG, "rotation angles must be finite");
+    if (!alm_in || !alm_out || !workspace) return fail(PSHT_ERR_ARG, "NULL array");
+    const size_t bytes = (size_t)ncomp * (size_t)(lmax + 1) * (size_t)(lmax + 2) / 2 * 16;
+    const char *a = (const char *)alm_in, *b = (const char *)alm_out;
+    if (a < b + bytes && b < a + bytes) return fail(PSHT_ERR_ARG, "alm_in and alm_out overlap");
+    if (ws_bytes < need) return fail(PSHT_ERR_WORKSPACE, "workspace smaller than psht_rotate_alm_workspace");
+    // log2(n!) for n = 0..2 lmax, per (device, lmax), kept for the process lifetime
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, double2 *> tables;
+    double2 *lf = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        auto key = std::make_pair(dev, lmax);
+        auto it = tables.find(key);
+        if (it == tables.end()) {
+            std::vector<double2> h(2 * (size_t)lmax + 1);
+            for (size_t n = 0; n < h.size(); ++n) {
+                const long double v = lgammal((long double)n + 1) / logl(2.0L);
+                h[n].x = (double)v;
+                h[n].y = (double)(v - (long double)h[n].x);
+            }
+            void *d = nullptr;
+            hipError_t e = hipMalloc(&d, h.size() * sizeof(double2));
+            if (e != hipSuccess) return device_fail(e, "log-factorial table");
+            e = hipMemcpy(d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(d);
+                return device_fail(e, "log-factorial table");
+            }
+            lf = (double2 *)d;
+            tables[key] = lf;
+        } else {
+            lf = it->second;
+        }
+    }
+    hipError_t e = psht::launch_rotate_alm(lmax, ncomp, alpha, beta, gamma, alm_in, alm_out, workspace, lf,
+                                           static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? PSHT_OK : device_fail(e, "rotation kernels");
+}
+
+psht_status psht_rotate_points(int64_t npoints, double alpha, double beta, double gamma, const double *theta,
+                               const double *phi, double *theta_out, double *phi_out, double *psi_out,
+                               void *hip_stream) {
+    if (npoints < 0) return fail(PSHT_ERR_ARG, "npoints < 0");
+    if (!std::isfinite(alpha) || !std::isfinite(beta) || !std::isfinite(gamma))
+        return fail(PSHT_ERR_ARG, "rotation angles must be finite");
+    if (npoints > 0 && (!theta || !phi || !theta_out || !phi_out || !psi_out))
+        return fail(PSHT_ERR_ARG, "NULL array");
+    psht::RotMatrix R;
+    const double ca = std::cos(alpha), sa = std::sin(alpha), cb = std::cos(beta), sb = std::sin(beta),
+                 cg = std::cos(gamma), sg = std::sin(gamma);
+    // Rz(alpha) Ry(beta) Rz(gamma)
+    const double Y[3][3] = {{cb * cg, -cb * sg, sb}, {sg, cg, 0.0}, {-sb * cg, sb * sg, cb}};
+    for (int c = 0; c < 3; ++c) {
+        R.r[0][c] = ca * Y[0][c] - sa * Y[1][c];
+        R.r[1][c] = sa * Y[0][c] + ca * Y[1][c];
+        R.r[2][c] = Y[2][c];
+    }
+    hipError_t e = psht::launch_rotate_points(npoints, R, theta, phi, theta_out, phi_out, psi_out,
+                                              static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? PSHT_OK : device_fail(e, "point rotation kernel");
+}
+
+psht_status psht_spin_phase(int64_t npoints, int spin, int sign, int fp32, const double *psi, void *map,
+                            void *hip_stream) {
+    if (npoints < 0 || (sign != 1 && sign != -1) || (fp32 != 0 && fp32 != 1))
+        return fail(PSHT_ERR_ARG, "need npoints >= 0, sign +-1, fp32 0 or 1");
+    if (npoints > 0 && (!psi || !map)) return fail(PSHT_ERR_ARG, "NULL array");
+    hipError_t e = psht::launch_spin_phase(npoints, (double)sign * spin, fp32, psi, map,
+                                           static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? PSHT_OK : device_fail(e, "spin phase kernel");
+}
 
 psht_status psht_great_circle_spectrum(int lmax, int spin, const double *cl, double *cm) {
     if (lmax < 0 || spin < 0 || spin > lmax || !cl || !cm) return fail(PSHT_ERR_ARG, "bad arguments");

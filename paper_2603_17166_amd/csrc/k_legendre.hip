@@ -26,6 +26,7 @@
 // less than the 2^800 of headroom above the renormalisation threshold).
 #include <cstdlib>
 
+#include "lane_ops.h"
 #include "leg_common.h"
 #include "psht_internal.h"
 
@@ -392,24 +393,6 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
 // ---------------------------------------------------------------- adjoint
 
 
-// Swap the upper 32 lanes of x with the lower 32 lanes of y (64-bit values).
-__device__ inline void swap32(double &x, double &y) {
-    unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
-    auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
-    auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
-    x = __hiloint2double(hi[0], lo[0]);
-    y = __hiloint2double(hi[1], lo[1]);
-}
-
-// Same at 16-lane granularity inside each half of the wave.
-__device__ inline void swap16(double &x, double &y) {
-    unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
-    auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
-    auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
-    x = __hiloint2double(hi[0], lo[0]);
-    y = __hiloint2double(hi[1], lo[1]);
-}
-
 // Fold of one l-step's four lane sums c0..c3 (Re and Im of the + and - sums)
 // into the transposed reduction, as soon as they are computed: a 32-lane swap
 // keeps component c + 2 bit5(i) in lane i, summed over lanes i and i ^ 32; the
@@ -482,18 +465,6 @@ __device__ inline void adj_renorm(LegState<R, SPIN> &S, const double2 *Fp, const
             fmi[r] = -vm.y;
         }
     }
-}
-
-// x from lane i ^ 1 and i ^ 2 of the quad (DPP quad permutations, 64-bit values).
-__device__ inline double quad_xor1(double x) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ inline double quad_xor2(double x) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x4E, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x4E, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
 }
 
 // ------------------------------------------------------- segmented adjoint

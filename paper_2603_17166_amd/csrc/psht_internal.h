@@ -212,6 +212,18 @@ hipError_t launch_phi_adjoint(const psht_plan_s &p, const void *U, void *V, hipS
 hipError_t launch_interp(const psht_plan_s &p, const void *U, void *map, hipStream_t st);
 hipError_t launch_spread(const psht_plan_s &p, const void *map, void *U, hipStream_t st);
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
+
+// Patch-frame rotation (k_rotate.hip): R = Rz(alpha) Ry(beta) Rz(gamma).
+struct RotMatrix {
+    double r[3][3];
+};
+// Coefficients: workspace ws of nc (lmax + 1)(2 lmax + 1) complex doubles; lf:
+// device table of log2(n!) as double-double, n = 0..2 lmax.
+hipError_t launch_rotate_alm(int lmax, int nc, double alpha, double beta, double gamma, const void *alm_in,
+                             void *alm_out, void *ws, const double2 *lf, hipStream_t st);
+hipError_t launch_rotate_points(int64_t n, const RotMatrix &R, const double *theta, const double *phi,
+                                double *theta_out, double *phi_out, double *psi_out, hipStream_t st);
+hipError_t launch_spin_phase(int64_t n, double ks, int fp32, const double *psi, void *map, hipStream_t st);
 hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, const void *in, void *out,
                            hipStream_t st);
 

@@ -1,0 +1,147 @@
+"""Patch-frame rotation on the GPU (Sec. II, step 1) against the oracle.
+
+* Coefficients: element by element against the oracle's Wigner-D rotation
+  for lmax 0 .. 130 (several 8-order tiles and 128-column wavefronts with
+  ragged ends), one and two components, angles including beta = 0, pi, a tiny
+  beta (seeds far below the double range) and negative beta; at lmax 4096
+  (the size of the largest workload) on sampled orders, each computed by the
+  oracle's d^l_{m m'} over all m'.
+* Points and spin basis: against the oracle's explicit basis vectors.
+* End to end: coefficients and points given in an equatorial frame, a disc
+  of 6 deg around (theta_c, phi_c); rotation + plan + spin phase on the GPU
+  against the oracle's synthesis and adjoint in the original frame.
+Bar: 1e-12 relative for the rotation (FP64), 10 eps for the transforms."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2603_17166_amd import rotate as rot
+from paper_2603_17166_amd import synthetic as syn
+from paper_2603_17166_amd.plan import Plan
+
+pytestmark = pytest.mark.gpu
+DEG = math.pi / 180
+ANGLES = [(0.3, 1.1, -0.7), (2.0, math.pi, 0.4), (-1.2, 1e-3, 3.0), (0.0, -2.61, -0.9), (0.7, 0.0, 0.2),
+          (5.0, 0.5 * math.pi, -4.0)]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _alm(lmax, nc, seed):
+    a = syn.gaussian_alm(lmax, 0, seed)[:nc].copy()
+    m, _ = syn.alm_m_l(lmax)
+    a[:, m == 0] = a[:, m == 0].real
+    return a
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 7, 40, 130])
+@pytest.mark.parametrize("nc", [1, 2])
+def test_rotate_alm_vs_oracle(lmax, nc):
+    a = _alm(lmax, nc, 100 + lmax)
+    for ang in ANGLES:
+        say("rotate_alm lmax %d nc %d angles %s" % (lmax, nc, ang))
+        got = rot.rotate_alm(torch.as_tensor(a).cuda(), lmax, *ang).cpu().numpy()
+        ref = oracle.rotate_alm(a, lmax, *ang)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-12, (ang, err)
+    torch.cuda.synchronize()
+
+
+def _oracle_order(a, lmax, m, alpha, beta, gamma):
+    """a'_lm, l = m..lmax, for one order m from the oracle's d^l_{m m'}."""
+    out = np.zeros((a.shape[0], lmax + 1), dtype=np.complex128)
+    l = np.arange(lmax + 1)
+    for mp in range(-lmax, lmax + 1):
+        k = abs(mp)
+        lo = max(m, k)
+        if lo > lmax:
+            continue
+        d = oracle.wigner_d(lmax, m, mp, beta)[lo:]
+        v = a[:, oracle.alm_index(lmax, l[lo:], k)]
+        if mp < 0:
+            v = (-1) ** k * np.conj(v)
+        if k == 0:
+            v = v.real + 0j
+        out[:, lo:] += d * np.exp(-1j * mp * gamma) * v
+    return np.exp(-1j * m * alpha) * out[:, m:]
+
+
+def test_rotate_alm_lmax4096_sampled_orders():
+    lmax = 4096
+    ang = rot.patch_angles(147.0 * DEG, 0.3, 0.25)
+    a = syn.gaussian_alm(lmax, 2, 4242)
+    say("rotate_alm lmax 4096, two components")
+    got = rot.rotate_alm(torch.as_tensor(a).cuda(), lmax, *ang).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    for m in (0, 1, 37, 1500, 4000, 4096):
+        ref = _oracle_order(a, lmax, m, *ang)
+        g = got[:, oracle.alm_index(lmax, np.arange(m, lmax + 1), m)]
+        err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        say("  m %d: max rel err %.2e" % (m, err))
+        assert err <= 1e-11
+    # unitarity over all orders
+    na, nb = oracle.alm_dot(a, a, lmax), oracle.alm_dot(got, got, lmax)
+    assert abs(nb / na - 1) < 1e-12
+
+
+def test_rotate_points_and_spin_phase():
+    th, ph = syn.uniform_cap(5000, 3.1, 77)
+    th, ph = th.copy(), ph - 7.0   # phi outside [0, 2 pi)
+    for ang in ANGLES:
+        t2, p2, psi = rot.rotate_points(torch.as_tensor(th).cuda(), torch.as_tensor(ph).cuda(), *ang)
+        rt, rp, rpsi = oracle.rotate_points(th, ph, *ang)
+        t2, p2, psi = t2.cpu().numpy(), p2.cpu().numpy(), psi.cpu().numpy()
+        assert np.max(np.abs(t2 - rt)) < 1e-13
+        away = np.sin(rt) > 1e-6
+        assert np.max(np.abs(np.angle(np.exp(1j * (p2 - rp)))[away])) < 1e-12
+        assert np.all((p2 >= 0) & (p2 < 2 * math.pi))
+        assert np.max(np.abs(np.angle(np.exp(1j * (psi - rpsi)))[away])) < 1e-12
+    for dt, tol in ((torch.complex128, 1e-15), (torch.complex64, 1e-6)):
+        f = syn.gaussian_map(th.shape[0], 78)
+        fm = torch.as_tensor(f).to(dt).cuda()
+        psi_t = torch.as_tensor(rpsi).cuda()
+        rot.spin_phase(fm, psi_t, 2, -1)
+        want = f * np.exp(-2j * rpsi)
+        assert np.max(np.abs(fm.cpu().numpy() - want)) < tol * 10
+
+
+@pytest.mark.parametrize("lmax,spin,eps,prec", [(1024, 2, 1e-10, "fp64"), (1024, 0, 1e-10, "fp64"),
+                                                (2048, 2, 1e-5, "fp32")])
+def test_equatorial_frame_end_to_end(lmax, spin, eps, prec):
+    """Synthesis and adjoint of a field given in another frame: rotate the
+    coefficients and points into the patch frame, transform there, and turn
+    the spin basis back; against the oracle in the original frame."""
+    theta_c, phi_c = 2.2, 4.0
+    ang = rot.patch_angles(theta_c, phi_c)
+    inv = rot.inverse_angles(*ang)
+    # a 6 deg disc around (theta_c, phi_c): points drawn at the pole, moved there
+    th0, ph0 = syn.uniform_cap(300, 6 * DEG, 500 + lmax)
+    th_g, ph_g, _ = oracle.rotate_points(th0, ph0, *inv)
+    a = syn.gaussian_alm(lmax, spin, 600 + lmax)
+    say("end to end lmax %d spin %d %s" % (lmax, spin, prec))
+    t2, p2, psi = rot.rotate_points(torch.as_tensor(th_g).cuda(), torch.as_tensor(ph_g).cuda(), *ang)
+    assert float(t2.max()) < 6.001 * DEG
+    plan = Plan(t2, p2, lmax, spin, eps, prec)
+    a_patch = rot.rotate_alm(torch.as_tensor(a).cuda(), lmax, *ang)
+    f = plan.synth(a_patch)
+    rot.spin_phase(f, psi, spin, -1)
+    ref = oracle.synth(a, th_g, ph_g, lmax, spin)
+    e1 = float(np.linalg.norm(f.cpu().numpy() - ref) / np.linalg.norm(ref))
+    fp32 = bool(plan.info["map_is_fp32"])
+    g = syn.gaussian_map(th_g.shape[0], 700 + lmax)
+    gt = torch.as_tensor(g.astype(np.complex64 if fp32 else np.complex128)).cuda()
+    rot.spin_phase(gt, psi, spin, 1)          # adjoint of the phase exp(-i s psi)
+    adj = rot.rotate_alm(plan.adjoint(gt), lmax, *inv).cpu().numpy()
+    aref = oracle.adjoint(g.astype(np.complex64 if fp32 else np.complex128).astype(np.complex128), th_g, ph_g,
+                          lmax, spin)
+    d = adj - aref
+    e2 = math.sqrt(oracle.alm_dot(d, d, lmax) / oracle.alm_dot(aref, aref, lmax))
+    say("  synth %.2e adjoint %.2e (eps %g)" % (e1, e2, eps))
+    assert e1 <= 10 * eps and e2 <= 10 * eps
+    plan.close()
