@@ -102,9 +102,10 @@ def stage_work(w, info) -> dict:
     }
 
 
-STAGE_KERNEL = {"leg_synth": "psht::k_leg_synth", "leg_adj": "psht::k_leg_adjoint", "theta_synth": "psht::k_theta_synth",
-                "theta_adj": "psht::k_theta_adjoint", "phi_synth": "psht::k_phi_synth", "phi_adj": "psht::k_phi_adjoint",
-                "interp": "psht::k_interp", "spread": "psht::k_spread"}
+STAGE_KERNEL = {"leg_synth": ("psht::k_leg_synth<",), "leg_adj": ("psht::k_leg_adj_seg6<", "psht::k_leg_adj_seg4<"),
+                "theta_synth": ("psht::k_theta_synth<",), "theta_adj": ("psht::k_theta_adjoint<",),
+                "phi_synth": ("psht::k_phi_synth<",), "phi_adj": ("psht::k_phi_adjoint<",),
+                "interp": ("psht::k_interp<",), "spread": ("psht::k_spread<",)}
 
 
 def measured_traffic(stage: str, workload: str):
@@ -119,7 +120,7 @@ def measured_traffic(stage: str, workload: str):
     with open(path) as fh:
         table = json.load(fh).get(workload, {})
     for name, e in table.items():
-        if not name.startswith(STAGE_KERNEL[stage] + "<"):
+        if not name.startswith(STAGE_KERNEL[stage]):
             continue
         h = hashlib.sha256()
         for f in e["sources"]:
@@ -411,6 +412,94 @@ def full_sky_speedup(workloads, steps: int, log) -> dict:
     return out
 
 
+def rotation_triples(lmax: int) -> int:
+    """(l, m, m') with 0 <= m <= l, |m'| <= l, l <= lmax: the recurrence steps of the rotation."""
+    m = np.arange(lmax + 1)[:, None]
+    mp = np.abs(np.arange(-lmax, lmax + 1))[None, :]
+    return int(np.sum(lmax + 1 - np.maximum(m, mp)))
+
+
+def patch_frame(lmax: int, npoints: int, steps: int, log) -> dict:
+    """Rotation into the patch frame (Sec. II, step 1) at the largest workload's
+    size: coefficients of both components at lmax 4096 (FP64 ALU bound:
+    16 FLOP per (l, m, m') step, 8 for the d recurrence and 4 per component
+    for the accumulation) and the points with their spin angle (HBM bound:
+    16 bytes read and 24 written per point)."""
+    import torch
+
+    from paper_2603_17166_amd import rotate as rot
+
+    ang = rot.patch_angles(147.0 * math.pi / 180, 0.3, 0.25)
+    a = torch.as_tensor(syn.gaussian_alm(lmax, 2, 4242), device="cuda")
+    rot.rotate_alm(a, lmax, *ang)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        out = rot.rotate_alm(a, lmax, *ang)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    tri = rotation_triples(lmax)
+    tflops = 16.0 * tri / (ms * 1e-3) / 1e12
+    del out
+    th = torch.rand(npoints, dtype=torch.float64, device="cuda") * 0.3
+    ph = torch.rand(npoints, dtype=torch.float64, device="cuda") * 6.28
+    rot.rotate_points(th, ph, *ang)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(steps):
+        rot.rotate_points(th, ph, *ang)
+    ev[1].record()
+    torch.cuda.synchronize()
+    pms = ev[0].elapsed_time(ev[1]) / steps
+    gbs = 40.0 * npoints / (pms * 1e-3) / 1e9
+    log("patch frame: rotate_alm lmax %d x2: %.2f ms (%.1f TFLOP/s FP64); points %d: %.3f ms (%.0f GB/s)" % (
+        lmax, ms, tflops, npoints, pms, gbs))
+    return {"rotate_alm": {"lmax": lmax, "components": 2, "ms": ms, "triples": tri,
+                           "roofline": {"bound": "alu", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s",
+                                        "frac": tflops / 78.6, "flop_per_triple": 16}},
+            "rotate_points": {"npoints": npoints, "ms": pms,
+                              "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                                           "frac": gbs / 8000.0, "bytes_per_point": 40}}}
+
+
+def plan_rules(w, steps: int, log) -> dict:
+    """Lmax rules on one workload: eq. Lmax2, the least-work rule, and Lmax
+    tuned to the spectrum of the seeded coefficients (C_l = (l+1)^-2, Sec.
+    II.D); one synthesis + one adjoint each, error against the eq. Lmax2 plan."""
+    import torch
+
+    from paper_2603_17166_amd.plan import Plan
+
+    a = torch.as_tensor(w.alm(), device="cuda")
+    l = np.arange(w.lmax + 1)
+    out, ref = {}, None
+    for name, kw in (("band", {}), ("cost", {"lmax_rule": "cost"}), ("tuned", {"cl": 1.0 / (1.0 + l) ** 2})):
+        t0 = time.time()
+        plan = Plan(w.theta, w.phi, w.lmax, w.spin, w.epsilon, w.precision, **kw)
+        plan_s = time.time() - t0
+        fmap = torch.as_tensor(w.adjoint_map(np.complex64 if plan.info["map_is_fp32"] else np.complex128),
+                               device="cuda")
+        om = torch.empty(w.npoints, dtype=plan.map_dtype, device="cuda")
+        oa = torch.empty_like(a)
+        plan.workspace(1)
+        time_steps(plan, a, fmap, om, oa, 1, "both")
+        t = time_steps(plan, a, fmap, om, oa, steps, "both")
+        f = plan.synth(a)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = f.clone()
+        err = float(torch.linalg.vector_norm(f - ref) / torch.linalg.vector_norm(ref))
+        out[name] = {"ms_per_step": t * 1e3 / steps, "Lmax": plan.info["Lmax"], "eps_apo": plan.info["eps_apo"],
+                     "legendre_triples": plan.info["legendre_triples"], "plan_s": plan_s,
+                     "predicted_error": plan.info["predicted_error"], "synth_rel_diff_vs_band": err}
+        log("Lmax rule %s: Lmax %d, %.3f ms per synth+adjoint, diff vs band %.1e" % (
+            name, plan.info["Lmax"], t * 1e3 / steps, err))
+        plan.close()
+    return out
+
+
 def batched_maps(w, nmaps: int, steps: int, check_points: int, log) -> dict:
     """nmaps coefficient sets / maps per call on one plan (the Legendre
     synthesis runs as one MFMA pass per group of up to 8 maps)."""
@@ -585,6 +674,7 @@ def main() -> int:
     ap.add_argument("--serve-fp64-single", type=int, default=300,
                     help="requests of the served mix also run one at a time on FP64 plans")
     ap.add_argument("--full-sky-only", action="store_true", help="only the full-sky vs partial comparison")
+    ap.add_argument("--patch-frame-only", action="store_true", help="only the rotation into the patch frame")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -606,6 +696,9 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
+        return 0
+    if args.patch_frame_only:
+        print(json.dumps(patch_frame(4096, 21_600_000, 3, log)), flush=True)
         return 0
     if args.full_sky_only:
         print(json.dumps(full_sky_speedup([syn.spt_like(2048), syn.spt_fine("fp64")], 3, log)), flush=True)
@@ -663,6 +756,8 @@ def main() -> int:
             ex["spt1658-l2048-s2-fp64"]["points_per_s"]
         line["other_workloads"] = ex
         line["full_sky_vs_partial"] = full_sky_speedup([w2, syn.spt_fine("fp64")], 3, log)
+        line["lmax_rules"] = plan_rules(w2, 3, log)
+        line["patch_frame"] = patch_frame(w64.lmax, w64.npoints, 3, log)
         line["served"] = served(args.serve_requests, args.serve_load, log, args.serve_fp64_single)
         if "served_vs_fp64_single" in line["served"]:
             line["served_vs_fp64_single"] = line["served"]["served_vs_fp64_single"]
