@@ -756,7 +756,7 @@ def main() -> int:
             ex["spt1658-l2048-s2-fp64"]["points_per_s"]
         line["other_workloads"] = ex
         line["full_sky_vs_partial"] = full_sky_speedup([w2, syn.spt_fine("fp64")], 3, log)
-        line["lmax_rules"] = plan_rules(w2, 3, log)
+        line["lmax_rules"] = plan_rules(w32, 3, log)
         line["patch_frame"] = patch_frame(w64.lmax, w64.npoints, 3, log)
         line["served"] = served(args.serve_requests, args.serve_load, log, args.serve_fp64_single)
         if "served_vs_fp64_single" in line["served"]:

@@ -178,7 +178,13 @@ psht_status psht_synth(psht_plan plan, int nmaps, const void *alm, void *map,
                        void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* Adjoint synthesis general (Sec. I) of nmaps maps into nmaps coefficient
- * sets; same layouts and workspace rule as psht_synth.  alm is overwritten. */
+ * sets; same layouts and workspace rule as psht_synth.  alm is overwritten.
+ * The spreading kernel adds its tile subgrids into the workspace, and plans
+ * whose orders hold more rings than one adjoint work item (ring groups, full
+ * sky at large lmax) add into alm, with device-scope floating-point atomic
+ * adds: workspace and alm must be ordinary (coarse-grained) device memory,
+ * as hipMalloc and torch's CUDA allocator return, not fine-grained, host or
+ * managed memory. */
 psht_status psht_adjoint(psht_plan plan, int nmaps, const void *map, void *alm,
                          void *workspace, size_t ws_bytes, void *hip_stream);
 

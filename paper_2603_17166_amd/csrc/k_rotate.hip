@@ -171,19 +171,6 @@ __device__ inline double4 rot_order_factors(int l, int m) {
     return make_double4(f1, M / (L * (L + 1)), (L + 1) * a0 / (L * a1), 0.0);
 }
 
-// x from lane i ^ 8 (DPP row rotation by 8 inside 16-lane rows) and from
-// lane i ^ 4 (ds_swizzle, bit mode with xor mask 4).
-__device__ inline double lane_xor8(double x) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x128, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x128, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ inline double lane_xor4(double x) {
-    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x101F);
-    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x101F);
-    return __hiloint2double(hi, lo);
-}
-
 // Exchange-halves round on n complex values (re[i], im[i]): lanes with the
 // given lane bit clear keep values 0..n/2-1, the others n/2..n-1, each summed
 // with the partner lane's copy.

@@ -1,6 +1,6 @@
 // Cross-lane exchanges of 64-bit values inside a 64-lane wavefront (gfx950):
 // 32- and 16-lane swaps (v_permlane32_swap / v_permlane16_swap) and DPP
-// permutations inside quads, used by the transposed reductions of the
+// permutations (xor 1, 2, 4, 8), used by the transposed reductions of the
 // Legendre adjoint and of the coefficient rotation.
 #pragma once
 
@@ -35,6 +35,20 @@ __device__ inline double quad_xor1(double x) {
 __device__ inline double quad_xor2(double x) {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x4E, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x4E, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// x from lane i ^ 4 (DPP: mirror inside each 8-lane half row, then reverse
+// each quad) and from lane i ^ 8 (DPP row rotation by 8 inside 16-lane rows).
+__device__ inline int lane_xor4_b32(int v) {
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+}
+__device__ inline double lane_xor4(double x) {
+    return __hiloint2double(lane_xor4_b32(__double2hiint(x)), lane_xor4_b32(__double2loint(x)));
+}
+__device__ inline double lane_xor8(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x128, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x128, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
