@@ -110,6 +110,10 @@ typedef struct {
     int32_t Lmax_rule;
     double predicted_error;
     int32_t window;     /* PSHT_WINDOW_* of the plan */
+    /* part of resident_bytes shared with every other plan of the same
+     * (lmax, spin): the Legendre recurrence table, freed with the last such
+     * plan (0 for psht_plan_geometry) */
+    size_t shared_bytes;
 } psht_plan_info;
 
 /* Options of psht_plan_create_ex / psht_plan_geometry_ex (NULL: all defaults,

@@ -52,7 +52,7 @@ class PlanInfo(ctypes.Structure):
         ("kernel_poly_err", ctypes.c_double),
         ("adj_segment", ctypes.c_int32), ("adj_waves", ctypes.c_int32), ("adj_rings_per_lane", ctypes.c_int32),
         ("adj_states", ctypes.c_int64), ("Lmax_rule", ctypes.c_int32), ("predicted_error", ctypes.c_double),
-        ("window", ctypes.c_int32),
+        ("window", ctypes.c_int32), ("shared_bytes", ctypes.c_size_t),
     ]
 
     def as_dict(self) -> dict:

@@ -125,6 +125,7 @@ void fill_info(const psht_plan_s &p, psht_plan_info *info) {
     info->legendre_triples = g.legendre_triples;
     info->npoints = p.npts;
     info->resident_bytes = p.resident + (p.leg ? p.leg->bytes : 0);
+    info->shared_bytes = p.leg ? p.leg->bytes : 0;
     info->workspace_bytes_per_map = p.ws_per_map;
     info->kernel_poly_err = g.es_poly_err;
     info->adj_segment = p.adj_seg;

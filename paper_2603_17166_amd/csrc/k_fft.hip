@@ -649,120 +649,130 @@ template <typename Fn> static void tier_dispatch(int n, Fn fn) {
 }
 
 template <typename T>
-static void theta_synth_t(const psht_plan_s &p, const StageArgs &a, const double2 *F, void *V, hipStream_t st) {
+static hipError_t theta_synth_t(const psht_plan_s &p, const StageArgs &a, const double2 *F, void *V, hipStream_t st) {
     typedef typename CT<T>::type C;
     const int n = p.theta_split ? p.g.N2 : p.g.Ntheta;
     const size_t lds = (size_t)n * sizeof(C);
+    hipError_t err = hipSuccess;
     tier_dispatch(n, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         if (p.theta_split) {
-            set_lds(k_theta_synth_split<T, MX>, lds);
+            if ((err = set_lds(k_theta_synth_split<T, MX>, lds)) != hipSuccess) return;
             hipLaunchKernelGGL((k_theta_synth_split<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)),
                                lds, st, a, F, static_cast<C *>(V));
         } else {
-            set_lds(k_theta_synth<T, MX>, lds);
+            if ((err = set_lds(k_theta_synth<T, MX>, lds)) != hipSuccess) return;
             hipLaunchKernelGGL((k_theta_synth<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)), lds,
                                st, a, F, static_cast<C *>(V));
         }
     });
+    return err;
 }
 
 template <typename T>
-static void theta_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *V, double2 *F, hipStream_t st) {
+static hipError_t theta_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *V, double2 *F, hipStream_t st) {
     typedef typename CT<T>::type C;
     const int n = p.theta_split ? p.g.N2 : p.g.Ntheta;
     const size_t lds = (size_t)n * sizeof(C);
+    hipError_t err = hipSuccess;
     tier_dispatch(n, [&](auto M) {
         constexpr int MX = decltype(M)::value;
         if (p.theta_split) {
-            set_lds(k_theta_adjoint_split<T, MX>, lds);
+            if ((err = set_lds(k_theta_adjoint_split<T, MX>, lds)) != hipSuccess) return;
             hipLaunchKernelGGL((k_theta_adjoint_split<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)),
                                dim3(fft_threads<T>(MX)), lds, st, a, static_cast<const C *>(V), F);
         } else {
-            set_lds(k_theta_adjoint<T, MX>, lds);
+            if ((err = set_lds(k_theta_adjoint<T, MX>, lds)) != hipSuccess) return;
             hipLaunchKernelGGL((k_theta_adjoint<T, MX>), dim3(xcd_grid(2 * p.g.mmax + 1)), dim3(fft_threads<T>(MX)),
                                lds, st, a, static_cast<const C *>(V), F);
         }
     });
+    return err;
 }
 
 template <typename T>
-static void phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V, void *U, hipStream_t st) {
+static hipError_t phi_synth_t(const psht_plan_s &p, const StageArgs &a, const void *V, void *U, hipStream_t st) {
     typedef typename CT<T>::type C;
     const int nh = p.g.Nphi / p.g.phi_parts;
     const size_t lds = (size_t)nh * sizeof(C);
+    hipError_t err = hipSuccess;
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
-        set_lds(k_phi_synth<T, MX>, lds);
+        if ((err = set_lds(k_phi_synth<T, MX>, lds)) != hipSuccess) return;
         hipLaunchKernelGGL((k_phi_synth<T, MX>), dim3(phi_grid(p.g.rows_used, p.g.phi_parts)), dim3(fft_threads<T>(MX)), lds,
                            st, a,
                            static_cast<const C *>(V), static_cast<C *>(U));
     });
+    return err;
 }
 
 template <typename T>
-static void phi_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *U, void *V, hipStream_t st) {
+static hipError_t phi_adjoint_t(const psht_plan_s &p, const StageArgs &a, const void *U, void *V, hipStream_t st) {
     typedef typename CT<T>::type C;
     const int nh = p.g.Nphi / p.g.phi_parts;
     const size_t lds = (size_t)nh * sizeof(C);
+    hipError_t err = hipSuccess;
     tier_dispatch(nh, [&](auto M) {
         constexpr int MX = decltype(M)::value;
-        set_lds(k_phi_adjoint<T, MX>, lds);
+        if ((err = set_lds(k_phi_adjoint<T, MX>, lds)) != hipSuccess) return;
         hipLaunchKernelGGL((k_phi_adjoint<T, MX>), dim3(phi_grid(p.g.rows_used, p.g.phi_parts)), dim3(fft_threads<T>(MX)),
                            lds, st, a,
                            static_cast<const C *>(U), static_cast<C *>(V));
     });
+    return err;
 }
 
 hipError_t launch_theta_synth(const psht_plan_s &p, const double *F, void *V, hipStream_t st) {
     const StageArgs a = stage_args(p);
     const double2 *F2 = reinterpret_cast<const double2 *>(F);
-    if (p.g.fp32) theta_synth_t<float>(p, a, F2, V, st);
-    else theta_synth_t<double>(p, a, F2, V, st);
+    const hipError_t e = p.g.fp32 ? theta_synth_t<float>(p, a, F2, V, st) : theta_synth_t<double>(p, a, F2, V, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 hipError_t launch_theta_adjoint(const psht_plan_s &p, const void *V, double *F, hipStream_t st) {
     const StageArgs a = stage_args(p);
     double2 *F2 = reinterpret_cast<double2 *>(F);
-    if (p.g.fp32) theta_adjoint_t<float>(p, a, V, F2, st);
-    else theta_adjoint_t<double>(p, a, V, F2, st);
+    const hipError_t e = p.g.fp32 ? theta_adjoint_t<float>(p, a, V, F2, st) : theta_adjoint_t<double>(p, a, V, F2, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 hipError_t launch_phi_synth(const psht_plan_s &p, const void *V, void *U, hipStream_t st) {
     const StageArgs a = stage_args(p);
-    if (p.g.fp32) phi_synth_t<float>(p, a, V, U, st);
-    else phi_synth_t<double>(p, a, V, U, st);
+    const hipError_t e = p.g.fp32 ? phi_synth_t<float>(p, a, V, U, st) : phi_synth_t<double>(p, a, V, U, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 hipError_t launch_phi_adjoint(const psht_plan_s &p, const void *U, void *V, hipStream_t st) {
     const StageArgs a = stage_args(p);
-    if (p.g.fp32) phi_adjoint_t<float>(p, a, U, V, st);
-    else phi_adjoint_t<double>(p, a, U, V, st);
+    const hipError_t e = p.g.fp32 ? phi_adjoint_t<float>(p, a, U, V, st) : phi_adjoint_t<double>(p, a, U, V, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template <typename T>
-static void fft_rows_t(const FftTable &t, int batch, int sign, const void *in, void *out, hipStream_t st) {
+static hipError_t fft_rows_t(const FftTable &t, int batch, int sign, const void *in, void *out, hipStream_t st) {
     typedef typename CT<T>::type C;
     const FftDev f = to_dev(t.f);
     const double2 *tw = reinterpret_cast<const double2 *>(t.d_tw);
     const size_t lds = (size_t)t.n * sizeof(C);
+    hipError_t err = hipSuccess;
     tier_dispatch(t.n, [&](auto M) {
         constexpr int MX = decltype(M)::value;
-        set_lds(k_fft_rows<T, MX>, lds);
+        if ((err = set_lds(k_fft_rows<T, MX>, lds)) != hipSuccess) return;
         hipLaunchKernelGGL((k_fft_rows<T, MX>), dim3(batch), dim3(fft_threads<T>(MX)), lds, st, f, sign, tw,
                            static_cast<const C *>(in), static_cast<C *>(out));
     });
+    return err;
 }
 
 hipError_t launch_fft_rows(const FftTable &t, int batch, int sign, bool fp32, const void *in, void *out,
                            hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    if (fp32) fft_rows_t<float>(t, batch, sign, in, out, st);
-    else fft_rows_t<double>(t, batch, sign, in, out, st);
+    const hipError_t e = fp32 ? fft_rows_t<float>(t, batch, sign, in, out, st) : fft_rows_t<double>(t, batch, sign, in, out, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

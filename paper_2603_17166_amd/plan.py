@@ -84,9 +84,12 @@ class Plan:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def close(self) -> None:
+    def close(self, sync: bool = True) -> None:
+        """Free the plan's device memory.  sync=False skips the device
+        synchronisation: only for a plan with no work in flight."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            torch.cuda.synchronize(self.device)
+            if sync:
+                torch.cuda.synchronize(self.device)
             _lib.load().psht_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 

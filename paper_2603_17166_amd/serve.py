@@ -13,7 +13,10 @@ every step:
      same plan and operation (up to `max_batch`), and admits them as one
      multi-map call if a slot is free and the memory budget (resident plans
      + in-flight workspaces, inputs and outputs) has room; idle plans are
-     evicted least-recently-used first to make room;
+     evicted least-recently-used first to make room.  A table that several
+     plans share (the library's Legendre table of one (lmax, spin)) is
+     counted once, and the budget is checked again once a plan exists (its
+     size before creation is an estimate);
   3. launches the batch on its slot's HIP stream, so batches on different
      slots overlap on the device.
 
@@ -69,9 +72,10 @@ class Request:
 class _PlanEntry:
     key: PlanKey
     handle: object
-    resident: int
+    resident: int          # bytes the plan holds alone
     busy: int = 0
     last_use: float = 0.0
+    shared: object = None  # key of a table shared with other plans, or None
 
 
 @dataclasses.dataclass(eq=False)
@@ -100,6 +104,7 @@ class Server:
         self.inflight: list = []
         self.free_slots = list(range(n_slots))
         self.plans: dict = {}
+        self.shared: dict = {}  # shared-table key -> [bytes, plans holding it]
         self.resident = 0
         self.inflight_bytes = 0
         self.completed: list = []
@@ -184,25 +189,48 @@ class Server:
             e = min(idle, key=lambda x: x.last_use)
             self.ex.drop_plan(e.handle)
             del self.plans[e.key]
-            self.resident -= e.resident
+            self._release(e)
             self.plans_evicted += 1
         return True
+
+    def _release(self, e: _PlanEntry) -> None:
+        self.resident -= e.resident
+        if e.shared is not None:
+            ent = self.shared[e.shared]
+            ent[1] -= 1
+            if ent[1] == 0:
+                self.resident -= ent[0]
+                del self.shared[e.shared]
 
     def _plan(self, key: PlanKey):
         e = self.plans.get(key)
         if e is not None:
             return e
         est = self.ex.plan_bytes_estimate(key)
+        shared_of = getattr(self.ex, "shared_of", None)
+        if shared_of is not None:
+            skey, sbytes = shared_of(key)
+            if skey in self.shared:
+                est = max(0, est - sbytes)  # already resident
         if not self._evict_for(est, None):
             return None
         try:
-            handle, resident = self.ex.create_plan(key)
+            res = self.ex.create_plan(key)
         except Exception as exc:  # invalid request (bad arguments, unknown patch)
             return exc
-        e = _PlanEntry(key, handle, int(resident), last_use=self.clock())
+        # (handle, bytes) or (handle, own bytes, shared-table key, shared bytes)
+        skey, sbytes = (res[2], int(res[3])) if len(res) > 2 else (None, 0)
+        e = _PlanEntry(key, res[0], int(res[1]), last_use=self.clock(), shared=skey)
         self.plans[key] = e
         self.resident += e.resident
+        if skey is not None:
+            ent = self.shared.setdefault(skey, [sbytes, 0])
+            if ent[1] == 0:
+                self.resident += sbytes
+            ent[1] += 1
         self.plans_created += 1
+        # the estimate may have been low: make room now if other plans are idle
+        self._evict_for(0, e)
         self.peak_bytes = max(self.peak_bytes, self._used())
         return e
 
@@ -260,6 +288,7 @@ class Server:
         for e in list(self.plans.values()):
             self.ex.drop_plan(e.handle)
         self.plans.clear()
+        self.shared.clear()
         self.resident = 0
 
 
@@ -345,19 +374,39 @@ class TorchExecutor:
     def add_patch(self, name: str, theta, phi) -> None:
         self.patches[name] = (theta, phi)
 
+    def shared_of(self, key: PlanKey):
+        """The Legendre recurrence table every plan of (lmax, spin) shares:
+        32 bytes per (l, m) and a seed per m."""
+        nalm = (key.lmax + 1) * (key.lmax + 2) // 2
+        return ("legendre", key.lmax, key.spin), nalm * 32 + (key.lmax + 1) * 16
+
     def plan_bytes_estimate(self, key: PlanKey) -> int:
+        """Bytes a plan will hold, from the host-side parameters: per point the
+        sorted coordinates and permutation (20 B) and the creation scratch
+        (24 B); the adjoint's recurrence states (40 B per ring and segment, at
+        most one segment per 64 degrees); the shared Legendre table; 1 MiB of
+        ring and FFT tables."""
+        from .plan import plan_geometry
+
         th, _ = self.patches[key.patch]
-        return int(len(th)) * 40  # sorted grid coordinates, permutation and tile keys; refined after creation
+        n = int(len(th))
+        ts = float(th.max()) if n else 0.0
+        info = plan_geometry(key.lmax, key.spin, ts, key.epsilon, key.precision)[0]
+        states = (info["Lmax"] + 1) * ((key.lmax + 64) // 64) * 40
+        return n * 44 + states + self.shared_of(key)[1] + (1 << 20)
 
     def create_plan(self, key: PlanKey):
         from .plan import Plan
 
         th, ph = self.patches[key.patch]
         p = Plan(th, ph, key.lmax, key.spin, key.epsilon, key.precision, device=self.device)
-        return p, p.info["resident_bytes"]
+        sb = int(p.info["shared_bytes"])
+        return p, p.info["resident_bytes"] - sb, self.shared_of(key)[0], sb
 
     def drop_plan(self, plan) -> None:
-        plan.close()
+        # the server drops only idle plans, whose batches have all retired:
+        # no device synchronisation is needed
+        plan.close(sync=False)
 
     def footprint(self, plan, op: str, n: int) -> int:
         from .plan import nalm

@@ -209,3 +209,56 @@ def test_closed_loop_and_percentiles():
     assert secs == pytest.approx(2.0)  # 4 batches of 2 on 2 slots
     assert percentile([3, 1, 2, 4], 50) == 2 and percentile([3, 1, 2, 4], 100) == 4
     assert percentile(list(range(1, 101)), 99) == 99
+
+
+class SharedExecutor(FakeExecutor):
+    """Plans of the same lmax share a table of `shared` bytes; the created
+    plans hold `actual` bytes of their own (more than the estimate)."""
+
+    def __init__(self, clock, shared=50, actual=None, **kw):
+        super().__init__(clock, **kw)
+        self.shared = shared
+        self.actual = actual if actual is not None else self.plan_bytes
+
+    def shared_of(self, key):
+        return ("tab", key.lmax), self.shared
+
+    def plan_bytes_estimate(self, key):
+        return self.plan_bytes + self.shared
+
+    def create_plan(self, key):
+        h, _ = super().create_plan(key)
+        return h, self.actual, ("tab", key.lmax), self.shared
+
+
+def test_shared_table_counted_once():
+    c = Clock()
+    ex = SharedExecutor(c, shared=50, plan_bytes=100)
+    srv = Server(ex, memory_budget=10_000, n_slots=1, max_batch=1, clock=c)
+    for p in ("a", "b", "c"):
+        srv.submit(K(p, l=64), "synth", 0)
+    srv.submit(K("a", l=128), "synth", 0)
+    srv.run_until_idle()
+    assert srv.resident == 4 * 100 + 2 * 50   # two tables (lmax 64 and 128), each once
+    assert srv.shared == {("tab", 64): [50, 3], ("tab", 128): [50, 1]}
+    # evicting plans releases a table with the last plan that holds it
+    assert srv._evict_for(10_000 - srv._used() + 150, None)   # the two least recently used plans go
+    assert srv.shared == {("tab", 64): [50, 1], ("tab", 128): [50, 1]} and srv.resident == 300
+    assert srv._evict_for(10**9, None) is False                # every plan goes, then nothing is left
+    assert srv.plans == {} and srv.shared == {} and srv.resident == 0
+
+
+def test_budget_rechecked_after_creation():
+    """The estimate (100 own bytes) is below what a plan holds (600): once the
+    second plan exists the budget is exceeded, and the idle first plan is
+    evicted (the shared table stays: the new plan holds it)."""
+    c = Clock()
+    ex = SharedExecutor(c, shared=50, plan_bytes=100, actual=600, per_map=0)
+    srv = Server(ex, memory_budget=1000, n_slots=1, max_batch=1, clock=c)
+    srv.submit(K("a"), "synth", 0)
+    srv.run_until_idle()
+    assert srv._used() == 650
+    srv.submit(K("b"), "synth", 0)
+    srv.run_until_idle()
+    assert srv.plans_evicted == 1 and set(ex.live_plans) == {K("b")}
+    assert srv._used() == 650 and srv.shared == {("tab", 64): [50, 1]}
