@@ -61,3 +61,39 @@ def test_spt1501_lmax4096_vs_stored_oracle(prec):
     assert np.all(at[:, l < w.spin] == 0)
     assert np.all(at[:, m == 0].imag == 0)
     plan.close()
+
+
+@pytest.mark.parametrize("prec,opts", [
+    ("fp32", {"cl": "red"}), ("fp64", {"cl": "red"}), ("fp64", {"window": "kb"}), ("fp64", {"window": "pswf"}),
+    ("fp32", {"window": "pswf"}), ("fp64", {"lmax_rule": "cost"}), ("fp32", {"lmax_rule": "cost"})])
+def test_spt1501_plan_options_vs_stored_oracle(prec, opts):
+    """The plan options at full size, against the same stored oracle results:
+    Lmax tuned to the coefficients' spectrum C_l = (l+1)^-2 (Sec. II.D), the
+    Kaiser-Bessel and Slepian bells (Sec. II.C) and the least-work Lmax rule
+    (footnote to eq. Lmax2); synthesis and adjoint within 10 eps."""
+    fx = np.load(FIXTURE)
+    w = syn.spt_fine(prec)
+    idx = fx["idx"]
+    kw = dict(opts)
+    if kw.get("cl") == "red":
+        kw["cl"] = 1.0 / (1.0 + np.arange(w.lmax + 1)) ** 2
+    plan = Plan(w.theta, w.phi, w.lmax, w.spin, w.epsilon, w.precision, **kw)
+    info = plan.info
+    say("spt1501 lmax 4096 %s %s: Lmax %d (rule %d), eps_apo %.4f, predicted %.2e" % (
+        prec, sorted(opts), info["Lmax"], info["Lmax_rule"], info["eps_apo"], info["predicted_error"]))
+    if "cl" in opts:
+        assert info["Lmax"] <= info["Lmax_rule"] and 0 < info["predicted_error"] <= 0.5 * w.epsilon
+    f = plan.synth(torch.as_tensor(w.alm(), device="cuda")).cpu().numpy()[idx].astype(np.complex128)
+    err = float(np.linalg.norm(f - fx["synth"]) / np.linalg.norm(fx["synth"]))
+    fp32 = bool(plan.info["map_is_fp32"])
+    g = torch.zeros(w.npoints, dtype=plan.map_dtype, device="cuda")
+    g[torch.as_tensor(idx, device="cuda")] = torch.as_tensor(
+        fx["adj_in"].astype(np.complex64 if fp32 else np.complex128), device="cuda")
+    at = plan.adjoint(g).cpu().numpy()
+    k = fx["adj_k"]
+    m, _ = syn.alm_m_l(w.lmax)
+    aerr = weighted_rel(at[:, k], fx["adj_out"], m[k])
+    say("  synth %.3e adjoint %.3e" % (err, aerr))
+    assert err <= 10 * w.epsilon and aerr <= 10 * w.epsilon
+    assert plan.dropped_points() == 0
+    plan.close()
