@@ -234,13 +234,16 @@ def adjoint(fmap, theta, phi, lmax, spin, epsilon, precision="auto"):
 
 
 def plan_geometry(lmax: int, spin: int, theta_star: float, epsilon: float, precision: str = "auto",
-                  full_sky: bool = False, window: str = "es", cl=None, lmax_rule: str = "band"):
-    """Host-only plan parameters for a cap of radius theta_star: (info, ring_theta, ring_w, ring_mmax)."""
+                  full_sky: bool = False, window: str = "es", cl=None, lmax_rule: str = "band", rings: bool = True):
+    """Host-only plan parameters for a cap of radius theta_star: (info, ring_theta, ring_w, ring_mmax);
+    with rings=False only info (no per-ring polar cut-offs, which take the longest)."""
     lib = _lib.load()
     info = _lib.PlanInfo()
     opts, _keep = _options(full_sky, window, cl, lmax_rule)
     _lib.check(lib.psht_plan_geometry_ex(lmax, spin, theta_star, epsilon, _lib.PREC[precision], ctypes.byref(opts),
                                          ctypes.byref(info), None, None, None, 0))
+    if not rings:
+        return info.as_dict(), None, None, None
     n = info.Lmax + 1
     th = np.zeros(n)
     w = np.zeros(n)
@@ -276,6 +279,8 @@ def fft(x: torch.Tensor, sign: int) -> torch.Tensor:
 def great_circle_spectrum(lmax: int, spin: int, cl) -> np.ndarray:
     """c_m, m = -lmax..lmax (index m + lmax), of an isotropic spin-`spin` field with power spectrum cl[0..lmax]."""
     c = np.ascontiguousarray(cl, dtype=np.float64)
+    if c.ndim != 1 or c.shape[0] < lmax + 1:
+        raise ValueError("cl must hold C_l for l = 0..lmax")
     out = np.zeros(2 * lmax + 1)
     dp = ctypes.POINTER(ctypes.c_double)
     _lib.check(_lib.load().psht_great_circle_spectrum(lmax, spin, c.ctypes.data_as(dp), out.ctypes.data_as(dp)))

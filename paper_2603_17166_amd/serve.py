@@ -391,7 +391,7 @@ class TorchExecutor:
         th, _ = self.patches[key.patch]
         n = int(len(th))
         ts = float(th.max()) if n else 0.0
-        info = plan_geometry(key.lmax, key.spin, ts, key.epsilon, key.precision)[0]
+        info = plan_geometry(key.lmax, key.spin, ts, key.epsilon, key.precision, rings=False)[0]
         states = (info["Lmax"] + 1) * ((key.lmax + 64) // 64) * 40
         return n * 44 + states + self.shared_of(key)[1] + (1 << 20)
 

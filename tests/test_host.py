@@ -267,6 +267,10 @@ def test_tuning_arguments():
         with pytest.raises(_lib.PshtError) as e:
             plan_geometry(128, 0, 0.2, 1e-8, cl=cl)
         assert e.value.code == _lib.PSHT_ERR_ARG
+    with pytest.raises(ValueError):
+        great_circle_spectrum(128, 0, np.ones(100))
+    with pytest.raises(_lib.PshtError):
+        great_circle_spectrum(10, 11, np.ones(11))
     # full-sky plans keep Lmax = lmax whatever the spectrum
     info = plan_geometry(128, 0, 0.2, 1e-8, full_sky=True, cl=np.ones(129))[0]
     assert info["Lmax"] >= 128 and info["predicted_error"] == -1.0
