@@ -481,7 +481,6 @@ __device__ inline void adj_renorm(LegState<R, SPIN> &S, const double2 *Fp, const
 // LDS, and wave 0 completes them over the waves and writes each output once
 // with a plain store (no atomics, no prior clear of the output).
 
-constexpr int kAdjMaxWaves = 4;
 constexpr int kAdjRedDoubles = 4 * 8 * 17;  // one wave's fold area per 8-step block
 
 struct AdjArgs {

@@ -145,3 +145,47 @@ def test_equatorial_frame_end_to_end(lmax, spin, eps, prec):
     say("  synth %.2e adjoint %.2e (eps %g)" % (e1, e2, eps))
     assert e1 <= 10 * eps and e2 <= 10 * eps
     plan.close()
+
+
+def test_rotation_edge_cases():
+    """Empty point sets and maps, in-place point rotation (outputs aliasing
+    the inputs), rotation by the identity, and the argument errors."""
+    from paper_2603_17166_amd import _lib
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    t2, p2, psi = rot.rotate_points(e, e, 0.3, 1.0, 0.2)
+    assert t2.numel() == 0 and psi.numel() == 0
+    rot.spin_phase(torch.empty(0, dtype=torch.complex128, device="cuda"), e, 2, 1)
+    # identity rotation
+    a = torch.as_tensor(_alm(33, 2, 900)).cuda()
+    ident = rot.rotate_alm(a, 33, 0.0, 0.0, 0.0)
+    assert float((ident - a).abs().max()) <= 1e-13 * float(a.abs().max())
+    # in place: theta_out / phi_out alias theta / phi
+    th, ph = syn.uniform_cap(1000, 2.0, 901)
+    ref = oracle.rotate_points(th, ph, 0.4, -1.3, 2.2)
+    tt, pp = torch.as_tensor(th).cuda(), torch.as_tensor(ph).cuda()
+    psi = torch.empty_like(tt)
+    lib = _lib.load()
+    _lib.check(lib.psht_rotate_points(tt.numel(), 0.4, -1.3, 2.2, tt.data_ptr(), pp.data_ptr(), tt.data_ptr(),
+                                      pp.data_ptr(), psi.data_ptr(), torch.cuda.current_stream().cuda_stream))
+    assert np.max(np.abs(tt.cpu().numpy() - ref[0])) < 1e-13
+    # errors
+    for args in [(-1, 2), (16384, 1), (10, 3)]:
+        with pytest.raises(_lib.PshtError):
+            import ctypes
+            n = ctypes.c_size_t()
+            _lib.check(lib.psht_rotate_alm_workspace(args[0], args[1], ctypes.byref(n)))
+    with pytest.raises(_lib.PshtError):   # input and output overlap
+        import ctypes
+        n = ctypes.c_size_t()
+        _lib.check(lib.psht_rotate_alm_workspace(33, 2, ctypes.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        _lib.check(lib.psht_rotate_alm(33, 2, 0.1, 0.2, 0.3, a.data_ptr(), a.data_ptr(), ws.data_ptr(), n.value,
+                                       torch.cuda.current_stream().cuda_stream))
+    with pytest.raises(_lib.PshtError):   # workspace too small
+        out = torch.empty_like(a)
+        _lib.check(lib.psht_rotate_alm(33, 2, 0.1, 0.2, 0.3, a.data_ptr(), out.data_ptr(), ws.data_ptr(), n.value - 1,
+                                       torch.cuda.current_stream().cuda_stream))
+    with pytest.raises(_lib.PshtError):   # non-finite angle
+        _lib.check(lib.psht_rotate_points(1, float("nan"), 0.0, 0.0, tt.data_ptr(), pp.data_ptr(), tt.data_ptr(),
+                                          pp.data_ptr(), psi.data_ptr(), torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()

@@ -362,3 +362,17 @@ def test_option_arguments():
         setattr(opts, field, bad)
         st = lib.psht_plan_geometry_ex(128, 0, 0.2, 1e-8, 0, ctypes.byref(opts), ctypes.byref(info), None, None, None, 0)
         assert st == _lib.PSHT_ERR_ARG
+
+
+def test_rotation_arguments_on_host():
+    """Host-side argument checks of the patch-frame calls (no device work)."""
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    assert lib.psht_rotate_alm_workspace(4096, 2, ctypes.byref(n)) == _lib.PSHT_OK
+    assert n.value == 2 * 4097 * 8193 * 16
+    for lmax, nc in [(-1, 2), (16384, 1), (10, 3), (10, 0)]:
+        assert lib.psht_rotate_alm_workspace(lmax, nc, ctypes.byref(n)) == _lib.PSHT_ERR_ARG
+    assert lib.psht_rotate_points(-1, 0.0, 0.0, 0.0, None, None, None, None, None, None) == _lib.PSHT_ERR_ARG
+    assert lib.psht_rotate_points(0, 0.0, 0.0, 0.0, None, None, None, None, None, None) == _lib.PSHT_OK
+    assert lib.psht_spin_phase(5, 2, 0, 0, None, None, None) == _lib.PSHT_ERR_ARG
+    assert lib.psht_spin_phase(0, 2, 1, 0, None, None, None) == _lib.PSHT_OK
