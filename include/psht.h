@@ -329,6 +329,25 @@ psht_status psht_plan_geometry_ex(int lmax, int spin, double theta_star, double 
 enum { PSHT_STAGE_LEGENDRE_SYNTH = 1, PSHT_STAGE_LEGENDRE_ADJOINT = 2 };
 psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, void *hip_stream);
 
+/* psht_stage with a workspace (at least workspace_bytes_per_map bytes,
+ * overwritten), for the stages after the Legendre step:
+ *   PSHT_STAGE_FOURIER_SYNTH : in = F complex128 [2 mmax + 1][Lmax + 1] (the
+ *       layout above), out = map [npoints] in the plan's precision: the
+ *       Theta stage (window w_j, doubled circle with the mirror sign
+ *       (-1)^(s+m), band limit |n| <= Lmax, Sec. I.B eq. Dnz), the phi stage
+ *       and the NUFFT interpolation, i.e. f_p = sum_m e^{i m phi_p}
+ *       sum_k D(Theta_p - Theta_k) G_k(m) up to the NUFFT error, with
+ *       G_j = w_j F_j, G_{N2-j} = (-1)^(s+m) w_j F_j, and F_j(m) taken as
+ *       zero for |m| above ring j's polar cut-off (Sec. II.A; the Legendre
+ *       stage writes zeros there).
+ *   PSHT_STAGE_FOURIER_ADJOINT : in = map, out = F' [2 mmax + 1][Lmax + 1];
+ *       the exact transpose of the stage above (spreading, phi and Theta
+ *       adjoints; zero above each ring's cut-off).
+ * The Legendre stages accept workspace = NULL.  Asynchronous on hip_stream. */
+enum { PSHT_STAGE_FOURIER_SYNTH = 3, PSHT_STAGE_FOURIER_ADJOINT = 4 };
+psht_status psht_stage_ex(psht_plan plan, int stage, const void *in, void *out, void *workspace, size_t ws_bytes,
+                          void *hip_stream);
+
 /* Batched complex FFT on device data, the kernel the Theta and phi stages use
  * (diagnostics and tests): `batch` transforms of length n (factors 2,3,5,7,11,13,
  * n <= 8192), contiguous rows, in place is allowed.

@@ -24,6 +24,8 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # PSHT_NOALLOC_SCRATCH_BYTES
 
 STAGE_LEGENDRE_SYNTH = 1
 STAGE_LEGENDRE_ADJOINT = 2
+STAGE_FOURIER_SYNTH = 3
+STAGE_FOURIER_ADJOINT = 4
 
 # Every function the header declares; tests check that all are exported.
 EXPORTS = (
@@ -31,7 +33,7 @@ EXPORTS = (
     "psht_last_error", "psht_plan_geometry", "psht_stage", "psht_fft", "psht_legendre_column",
     "psht_plan_set_timing", "psht_plan_timing", "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc",
     "psht_plan_check", "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum",
-    "psht_rotate_alm_workspace", "psht_rotate_alm", "psht_rotate_points", "psht_spin_phase",
+    "psht_rotate_alm_workspace", "psht_rotate_alm", "psht_rotate_points", "psht_spin_phase", "psht_stage_ex",
 )
 
 STAGE_NAMES = ("leg_synth", "theta_synth", "phi_synth", "interp", "grid_zero", "spread", "phi_adj", "theta_adj",
@@ -104,6 +106,7 @@ def load() -> ctypes.CDLL:
     lib.psht_plan_destroy.argtypes = [vp]
     lib.psht_plan_destroy.restype = None
     d = ctypes.c_double
+    lib.psht_stage_ex.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_rotate_alm_workspace.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     lib.psht_rotate_alm.argtypes = [ctypes.c_int, ctypes.c_int, d, d, d, vp, vp, vp, ctypes.c_size_t, vp]
     lib.psht_rotate_points.argtypes = [ctypes.c_int64, d, d, d, vp, vp, vp, vp, vp, vp]
@@ -121,7 +124,8 @@ def load() -> ctypes.CDLL:
                  "psht_stage", "psht_fft", "psht_legendre_column", "psht_plan_set_timing", "psht_plan_timing",
                  "psht_adjoint_grad", "psht_synth_grad", "psht_synth_noalloc", "psht_plan_check",
                  "psht_plan_create_ex", "psht_plan_geometry_ex", "psht_great_circle_spectrum",
-                 "psht_rotate_alm_workspace", "psht_rotate_alm", "psht_rotate_points", "psht_spin_phase"):
+                 "psht_rotate_alm_workspace", "psht_rotate_alm", "psht_rotate_points", "psht_spin_phase",
+                 "psht_stage_ex"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

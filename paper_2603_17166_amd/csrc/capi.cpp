@@ -852,6 +852,35 @@ psht_status psht_plan_geometry_ex(int lmax, int spin, double theta_star, double 
     }
 }
 
+psht_status psht_stage_ex(psht_plan plan, int stage, const void *in, void *out, void *workspace, size_t ws_bytes,
+                          void *hip_stream) {
+    if (stage == PSHT_STAGE_LEGENDRE_SYNTH || stage == PSHT_STAGE_LEGENDRE_ADJOINT)
+        return psht_stage(plan, stage, in, out, hip_stream);
+    if (stage != PSHT_STAGE_FOURIER_SYNTH && stage != PSHT_STAGE_FOURIER_ADJOINT)
+        return fail(PSHT_ERR_ARG, "unknown stage");
+    if (!plan || !in || !out) return fail(PSHT_ERR_ARG, "plan, in or out is NULL");
+    if (!check_ws(*plan, 1, workspace, ws_bytes))
+        return fail(PSHT_ERR_WORKSPACE, "workspace smaller than workspace_bytes_per_map");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    psht_plan_s &P = *plan;
+    char *ws = static_cast<char *>(workspace);
+    void *V = ws + P.ws_F;
+    void *U = ws + P.ws_F + P.ws_V;
+    hipError_t e;
+    if (stage == PSHT_STAGE_FOURIER_SYNTH) {
+        e = psht::launch_theta_synth(P, static_cast<const double *>(in), V, st);
+        if (e == hipSuccess) e = psht::launch_phi_synth(P, V, U, st);
+        if (e == hipSuccess) e = psht::launch_interp(P, U, out, st);
+    } else {
+        e = psht::launch_fill_zero(U, P.ws_U, st);
+        if (e == hipSuccess) e = psht::launch_spread(P, in, U, st);
+        if (e == hipSuccess) e = psht::launch_phi_adjoint(P, U, V, st);
+        if (e == hipSuccess) e = psht::launch_theta_adjoint(P, V, static_cast<double *>(out), st);
+    }
+    if (e != hipSuccess) return device_fail(e, "stage launch");
+    return PSHT_OK;
+}
+
 psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, void *hip_stream) {
     if (!plan || !in || !out) return fail(PSHT_ERR_ARG, "plan, in or out is NULL");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);

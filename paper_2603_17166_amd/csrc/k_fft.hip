@@ -418,7 +418,8 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_adjoint(StageArg
             re += sig * (double)u.x;
             im += sig * (double)u.y;
         }
-        const double wj = a.ring_w[j];
+        // orders above the ring's polar cut-off: zero, as the synthesis reads them
+        const double wj = a.ring_mmax[j] >= am ? a.ring_w[j] : 0.0;
         Fm[j] = make_double2(re * wj, im * wj);
     }
 }
@@ -479,7 +480,8 @@ __global__ __launch_bounds__(fft_threads<T>(MAXN)) void k_theta_adjoint_split(St
             re += sig * (double)u.x;
             im += sig * (double)u.y;
         }
-        const double wj = a.ring_w[j];
+        // orders above the ring's polar cut-off: zero, as the synthesis reads them
+        const double wj = a.ring_mmax[j] >= am ? a.ring_w[j] : 0.0;
         Fm[j] = make_double2(re * wj, im * wj);
     }
 }

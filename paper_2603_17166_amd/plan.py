@@ -214,6 +214,24 @@ class Plan:
         out = torch.empty((2, nalm(self.lmax)), dtype=torch.complex128, device=self.device)
         return self.stage(_lib.STAGE_LEGENDRE_ADJOINT, F.contiguous(), out)
 
+    def _stage_ws(self, stage: int, inp: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        ws = self.workspace(1)
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().psht_stage_ex(self._h, stage, inp.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                                 ws.numel(), _stream(stream)))
+        return out
+
+    def fourier_synth(self, F: torch.Tensor) -> torch.Tensor:
+        """Map from per-ring Fourier coefficients F (2 mmax + 1, Lmax + 1): Theta and phi stages and interpolation."""
+        out = torch.empty(self.npoints, dtype=self.map_dtype, device=self.device)
+        return self._stage_ws(_lib.STAGE_FOURIER_SYNTH, F.to(torch.complex128).contiguous(), out)
+
+    def fourier_adjoint(self, fmap: torch.Tensor) -> torch.Tensor:
+        """Transpose of fourier_synth: (2 mmax + 1, Lmax + 1) complex128 from a map."""
+        out = torch.empty((2 * self.info["mmax"] + 1, self.info["Lmax"] + 1), dtype=torch.complex128,
+                          device=self.device)
+        return self._stage_ws(_lib.STAGE_FOURIER_ADJOINT, fmap.to(self.map_dtype).contiguous(), out)
+
 
 def synth(alm, theta, phi, lmax, spin, epsilon, precision="auto"):
     """One-shot synthesis (builds and drops a plan)."""
