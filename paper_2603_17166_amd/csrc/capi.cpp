@@ -732,7 +732,9 @@ psht_status psht_rotate_alm(int lmax, int ncomp, double alpha, double beta, doub
         (void)hipGetDevice(&dev);
         auto key = std::make_pair(dev, lmax);
         auto it = tables.find(key);
-        if (it == tables.end()) {
+        if (it != tables.end()) {
+            lf = it->second;
+        } else try {
             std::vector<double2> h(2 * (size_t)lmax + 1);
             for (size_t n = 0; n < h.size(); ++n) {
                 const long double v = lgammal((long double)n + 1) / logl(2.0L);
@@ -747,10 +749,10 @@ psht_status psht_rotate_alm(int lmax, int ncomp, double alpha, double beta, doub
                 (void)hipFree(d);
                 return device_fail(e, "log-factorial table");
             }
+            tables[key] = (double2 *)d;
             lf = (double2 *)d;
-            tables[key] = lf;
-        } else {
-            lf = it->second;
+        } catch (const std::bad_alloc &) {
+            return fail(PSHT_ERR_NOMEM, "host allocation failed");
         }
     }
     hipError_t e = psht::launch_rotate_alm(lmax, ncomp, alpha, beta, gamma, alm_in, alm_out, workspace, lf,
