@@ -467,7 +467,8 @@ def patch_frame(lmax: int, npoints: int, steps: int, log) -> dict:
 def plan_rules(w, steps: int, log) -> dict:
     """Lmax rules on one workload: eq. Lmax2, the least-work rule, and Lmax
     tuned to the spectrum of the seeded coefficients (C_l = (l+1)^-2, Sec.
-    II.D); one synthesis + one adjoint each, error against the eq. Lmax2 plan."""
+    II.D); one synthesis + one adjoint each, the synthesis' difference from
+    the eq. Lmax2 plan (both within epsilon of the exact map)."""
     import torch
 
     from paper_2603_17166_amd.plan import Plan
@@ -757,6 +758,7 @@ def main() -> int:
         line["other_workloads"] = ex
         line["full_sky_vs_partial"] = full_sky_speedup([w2, syn.spt_fine("fp64")], 3, log)
         line["lmax_rules"] = plan_rules(w32, 3, log)
+        line["lmax_rules_disc10"] = plan_rules(syn.served_disc(10.0, 4096, 2), 5, log)
         line["patch_frame"] = patch_frame(w64.lmax, w64.npoints, 3, log)
         line["served"] = served(args.serve_requests, args.serve_load, log, args.serve_fp64_single)
         if "served_vs_fp64_single" in line["served"]:
