@@ -331,7 +331,7 @@ def small_line(w, steps: int, warmup: int, log) -> dict:
            "synth_ms": r["synth_ms"], "adjoint_ms": r["adjoint_ms"], "plan_s": r["plan_s"],
            "roofline": roofline(w, r["info"], r["avg"]),
            "adjoint_segment": r["info"]["adj_segment"], "adjoint_waves": r["info"]["adj_waves"],
-           "adjoint_rings_per_lane": r["info"]["adj_rings_per_lane"]}
+           "adjoint_rings_per_lane": r["info"]["adj_rings_per_lane"], "synth_segment": r["info"]["syn_segment"]}
     out.update(stage_fractions(w, r["info"], r["avg"], r["step_ms_median"]))
     r["plan"].close()
     return out
@@ -676,6 +676,7 @@ def main() -> int:
                     help="requests of the served mix also run one at a time on FP64 plans")
     ap.add_argument("--full-sky-only", action="store_true", help="only the full-sky vs partial comparison")
     ap.add_argument("--patch-frame-only", action="store_true", help="only the rotation into the patch frame")
+    ap.add_argument("--served-only", action="store_true", help="only the served mix")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -700,6 +701,9 @@ def main() -> int:
         return 0
     if args.patch_frame_only:
         print(json.dumps(patch_frame(4096, 21_600_000, 3, log)), flush=True)
+        return 0
+    if args.served_only:
+        print(json.dumps(served(args.serve_requests, args.serve_load, log, args.serve_fp64_single)), flush=True)
         return 0
     if args.full_sky_only:
         print(json.dumps(full_sky_speedup([syn.spt_like(2048), syn.spt_fine("fp64")], 3, log)), flush=True)
@@ -732,7 +736,7 @@ def main() -> int:
                    "Lmax": info["Lmax"], "mmax": info["mmax"], "nufft_w": info["nufft_w"],
                    "grid": [info["rows_used"], info["nphi_grid"]], "legendre_triples": info["legendre_triples"],
                    "adjoint_segment": info["adj_segment"], "adjoint_waves": info["adj_waves"],
-                   "adjoint_rings_per_lane": info["adj_rings_per_lane"]},
+                   "adjoint_rings_per_lane": info["adj_rings_per_lane"], "synth_segment": info["syn_segment"]},
         "step_ms_median": d64["step_ms_median"], "step_ms_p90": d64["step_ms_p90"],
         "synth_points_per_s": d64["synth_points_per_s"], "adjoint_points_per_s": d64["adjoint_points_per_s"],
         "transforms_per_s": d64["transforms_per_s"], "plan_s": d64["plan_s"], "vs_oracle": d64["vs_oracle"],
@@ -741,7 +745,8 @@ def main() -> int:
                                   "grid": [info32["rows_used"], info32["nphi_grid"]],
                                   "legendre_triples": info32["legendre_triples"],
                                   "adjoint_segment": info32["adj_segment"], "adjoint_waves": info32["adj_waves"],
-                                  "adjoint_rings_per_lane": info32["adj_rings_per_lane"]}),
+                                  "adjoint_rings_per_lane": info32["adj_rings_per_lane"],
+                                  "synth_segment": info32["syn_segment"]}),
         "fp32_vs_fp64": d32["value"] / d64["value"],
     })
     if not args.no_cpu_baseline:

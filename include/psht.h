@@ -114,6 +114,11 @@ typedef struct {
      * (lmax, spin): the Legendre recurrence table, freed with the last such
      * plan (0 for psht_plan_geometry) */
     size_t shared_bytes;
+    /* Legendre synthesis work decomposition: 0, or (for plans whose per-order
+     * work items would leave most of the GPU idle) segments of syn_segment
+     * degrees per order, started from the adjoint's stored states, with
+     * syn_parts partial copies of the ring coefficients in the workspace */
+    int32_t syn_segment, syn_parts;
 } psht_plan_info;
 
 /* Options of psht_plan_create_ex / psht_plan_geometry_ex (NULL: all defaults,
@@ -343,7 +348,10 @@ psht_status psht_stage(psht_plan plan, int stage, const void *in, void *out, voi
  *   PSHT_STAGE_FOURIER_ADJOINT : in = map, out = F' [2 mmax + 1][Lmax + 1];
  *       the exact transpose of the stage above (spreading, phi and Theta
  *       adjoints; zero above each ring's cut-off).
- * The Legendre stages accept workspace = NULL.  Asynchronous on hip_stream. */
+ * The Legendre stages accept workspace = NULL and then run as psht_stage;
+ * with a workspace, PSHT_STAGE_LEGENDRE_SYNTH runs the work decomposition of
+ * psht_synth (degree segments when the plan's syn_segment is non-zero, their
+ * partial sums in the workspace).  Asynchronous on hip_stream. */
 enum { PSHT_STAGE_FOURIER_SYNTH = 3, PSHT_STAGE_FOURIER_ADJOINT = 4 };
 psht_status psht_stage_ex(psht_plan plan, int stage, const void *in, void *out, void *workspace, size_t ws_bytes,
                           void *hip_stream);

@@ -55,6 +55,7 @@ class PlanInfo(ctypes.Structure):
         ("adj_segment", ctypes.c_int32), ("adj_waves", ctypes.c_int32), ("adj_rings_per_lane", ctypes.c_int32),
         ("adj_states", ctypes.c_int64), ("Lmax_rule", ctypes.c_int32), ("predicted_error", ctypes.c_double),
         ("window", ctypes.c_int32), ("shared_bytes", ctypes.c_size_t),
+        ("syn_segment", ctypes.c_int32), ("syn_parts", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -135,6 +135,8 @@ void fill_info(const psht_plan_s &p, psht_plan_info *info) {
     info->Lmax_rule = g.Lmax_rule;
     info->predicted_error = g.predicted_error;
     info->window = g.window;
+    info->syn_segment = p.syn_seg;
+    info->syn_parts = p.syn_parts;
 }
 
 struct ScopedDevFree {
@@ -143,6 +145,79 @@ struct ScopedDevFree {
         if (p) (void)hipFree(p);
     }
 };
+
+// Degree-segmented synthesis.  The synthesis runs one wave per (order m,
+// chunk of 64 R rings) over all degrees of m; a small cap at high lmax has few
+// such items (a few hundred orders), each thousands of sequential steps long,
+// and leaves most of the GPU idle.  Such a plan cuts the degrees of every order
+// into segments of Ssyn = 2^k S degrees, S the adjoint's segment length, so
+// that every segment start has a state stored for the adjoint; segment k >= 1
+// of an order writes its own partial copy of F, which a second kernel adds in.
+// Ssyn is the largest such length for which the longest item costs at most a
+// third of the average work per wave slot (two waves per SIMD), as for the
+// adjoint; a plan whose longest order would get fewer than three segments is
+// not segmented.
+// The items use two rings per lane (one when PSHT_LEG_R fixes one): with
+// the parallelism from the segments, the longer per-step work beats the one
+// ring per lane of the plain list of such plans (lmax 4096, 5-degree disc:
+// 0.135 against 0.162 ms; equal within 2 us on the smallest plans).
+bool build_synth_segments(psht_plan_s &p, int ncu, const std::vector<int> &first, const std::vector<int> &last,
+                          const std::vector<int64_t> &soff_m, int S, hipStream_t st) {
+    const psht::Geometry &g = p.g;
+    const int lmax = g.lmax, s = g.spin, M = g.mmax;
+    p.syn_seg = 0;
+    p.syn_parts = 0;
+    p.n_syn_items = 0;
+    const int R = psht::leg_rings_per_lane() == 1 ? 1 : 2, chunk = 64 * R;
+    auto steps_cost = [&](int nr) { return (R > 1 && nr <= 64) ? 1.0 / R : 1.0; };
+    double total = 0.0;
+    for (int m = 0; m <= M; ++m) {
+        if (first[m] < 0 || std::max(m, s) > lmax) continue;
+        const int steps = lmax + 1 - std::max(m, s);
+        for (int jb = first[m]; jb <= last[m]; jb += chunk)
+            total += steps * steps_cost(std::min(chunk, last[m] + 1 - jb));
+    }
+    const double slots = (double)std::max(ncu, 1) * 4 * 2;
+    int Ssyn = S;
+    while ((double)Ssyn * 2 <= total / slots / 3.0) Ssyn *= 2;
+    if (const char *e = getenv("PSHT_SYN_SEG")) {  // tuning runs: a power-of-two multiple of S, 0 for none
+        const int v = atoi(e);
+        if (v == 0) Ssyn = lmax + 1;
+        else if (v >= S && v % S == 0 && ((v / S) & (v / S - 1)) == 0) Ssyn = v;
+    }
+    // at most two segments for the longest order: the plain work list (two
+    // measured within the noise of one, and cost the partial-sum launch)
+    if (3 * Ssyn > lmax + 1 - s) return true;
+    const int q = Ssyn / S;
+    std::vector<psht::SynSegItem> items;
+    int parts = 0;
+    for (int m = 0; m <= M; ++m) {
+        const int l0 = std::max(m, s);
+        if (first[m] < 0 || l0 > lmax) continue;
+        const int nr = last[m] - first[m] + 1;
+        const int nseg = (lmax + 1 - l0 + Ssyn - 1) / Ssyn;
+        parts = std::max(parts, nseg - 1);
+        for (int k = 0; k < nseg; ++k) {
+            const int la = l0 + k * Ssyn, lb = std::min(lmax + 1, la + Ssyn);
+            for (int jb = first[m]; jb <= last[m]; jb += chunk) {
+                const int je = std::min(jb + chunk, last[m] + 1);
+                // segment k starts at the adjoint's segment k q >= 1 (stored when nseg_adj > 1)
+                const int64_t so = k == 0 ? -1 : soff_m[m] + (int64_t)(k * q - 1) * nr + (jb - first[m]);
+                items.push_back(psht::SynSegItem{m, jb, je, la, lb, k, so});
+            }
+        }
+    }
+    // longest first (blocks are issued in order and dealt round-robin to the XCDs)
+    std::stable_sort(items.begin(), items.end(), [&](const psht::SynSegItem &u, const psht::SynSegItem &v) {
+        return (u.lb - u.la) * steps_cost(u.je - u.jb) > (v.lb - v.la) * steps_cost(v.je - v.jb);
+    });
+    if (!upload(p, p.d_syn_items, items, st)) return false;
+    p.n_syn_items = (int)items.size();
+    p.syn_seg = Ssyn;
+    p.syn_parts = parts;
+    p.syn_r = R;
+    return true;
+}
 
 // Work list and recurrence states of the segmented Legendre adjoint.
 //
@@ -206,6 +281,7 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
     bool accumulate = false;
     std::vector<psht::AdjItem> items;
     std::vector<psht::StateItem> sitems;
+    std::vector<int64_t> soff_m(M + 1, -1);  // first stored state of order m
     int64_t off = 0;
     for (int m = 0; m <= M; ++m) {
         const int l0 = std::max(m, s);
@@ -228,6 +304,7 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
         }
         if (nseg > 1) {
             for (int j0 = jb; j0 < je; j0 += 64) sitems.push_back(psht::StateItem{m, j0, jb, je, nseg, S, off});
+            soff_m[m] = off;
             off += (int64_t)(nseg - 1) * nr;
         }
     }
@@ -252,6 +329,10 @@ bool build_adjoint_segments(psht_plan_s &p, int ncu, hipStream_t st, psht::Error
         return false;
     }
     p.n_adj_items = (int)items.size();
+    if (!build_synth_segments(p, ncu, first, last, soff_m, S, st)) {
+        err = {PSHT_ERR_NOMEM, "uploading the synthesis work list"};
+        return false;
+    }
     hipError_t e = psht::launch_leg_adj_states(p, d_sitems, (int)sitems.size(), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -494,7 +575,9 @@ psht_status plan_create_impl(psht_plan *out, int lmax, int spin, int64_t npoints
     p.ws_F = align256((size_t)(2 * g.mmax + 1) * g.nring * 16);
     p.ws_V = align256((size_t)g.rows_used * (2 * g.mmax + 1) * cs);
     p.ws_U = align256((size_t)g.rows_used * g.Nphi * cs);
-    p.ws_per_map = p.ws_F + p.ws_V + p.ws_U;
+    // the synthesis' partial copies of F use the V and U region, which is
+    // free until the Legendre stage has added them into F
+    p.ws_per_map = p.ws_F + std::max(p.ws_V + p.ws_U, (size_t)p.syn_parts * p.ws_F);
     *out = plan.release();
     return PSHT_OK;
 }
@@ -583,7 +666,9 @@ psht_status psht::synth_run(psht_plan plan, int nmaps, const void *alm, void *ma
             });
         else
             e = timed(P, PSHT_T_LEG_SYNTH, st, [&] {
-                return psht::launch_leg_synth(P, a0, reinterpret_cast<double *>(ws0), mscale, st);
+                return psht::launch_leg_synth_parts(P, a0, reinterpret_cast<double *>(ws0),
+                                                    reinterpret_cast<double *>(ws0 + plan->ws_F),
+                                                    (int64_t)(plan->ws_F / 8), mscale, st);
             });
         for (int b = 0; b < nb && e == hipSuccess; ++b) {
             char *ws = ws0 + (size_t)b * plan->ws_per_map;
@@ -856,6 +941,21 @@ psht_status psht_plan_geometry_ex(int lmax, int spin, double theta_star, double 
 
 psht_status psht_stage_ex(psht_plan plan, int stage, const void *in, void *out, void *workspace, size_t ws_bytes,
                           void *hip_stream) {
+    if (stage == PSHT_STAGE_LEGENDRE_SYNTH && workspace != nullptr && plan != nullptr && plan->syn_seg > 0) {
+        // with a workspace: the work list synth_run uses (degree segments with
+        // partial copies of F in the workspace)
+        if (!in || !out) return fail(PSHT_ERR_ARG, "in or out is NULL");
+        if (!check_ws(*plan, 1, workspace, ws_bytes))
+            return fail(PSHT_ERR_WORKSPACE, "workspace smaller than workspace_bytes_per_map");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const psht::Geometry &g = plan->g;
+        hipError_t e = psht::launch_fill_zero(out, (size_t)(2 * g.mmax + 1) * g.nring * 16, st);
+        if (e == hipSuccess)
+            e = psht::launch_leg_synth_parts(*plan, in, static_cast<double *>(out), static_cast<double *>(workspace),
+                                             (int64_t)(plan->ws_F / 8), 1.0, st);
+        if (e != hipSuccess) return device_fail(e, "stage launch");
+        return PSHT_OK;
+    }
     if (stage == PSHT_STAGE_LEGENDRE_SYNTH || stage == PSHT_STAGE_LEGENDRE_ADJOINT)
         return psht_stage(plan, stage, in, out, hip_stream);
     if (stage != PSHT_STAGE_FOURIER_SYNTH && stage != PSHT_STAGE_FOURIER_ADJOINT)

@@ -97,6 +97,39 @@ __device__ inline void leg_init(const LegArgs &a, const LegItem &it, int lane, L
     }
 }
 
+// The R rings of this lane for order m, rings [jb + 64 r + lane] below je,
+// from recurrence states stored at plan time: the state of ring j at index
+// soff + (j - jb), {mu+_l, mu+_{l-1}, mu-_l, mu-_{l-1}} and the scales {k+, k-}.
+template <int R, bool SPIN>
+__device__ inline void leg_init_stored(const LegArgs &a, int m, int jb, int je, int lane, const double4 *st_mu,
+                                       const int2 *st_k, int64_t soff, LegState<R, SPIN> &S) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = jb + r * 64 + lane;
+        S.act[r] = (j < je) && (a.ring_mmax[j] >= m);
+        S.y[r] = 0.0;
+        S.up[r] = S.upp[r] = S.um[r] = S.ump[r] = 0.0;
+        S.kp[r] = S.km[r] = 0;
+        if (S.act[r]) {
+            const int64_t q = soff + (j - jb);
+            const double4 v = st_mu[q];
+            const int2 k = st_k[q];
+            S.y[r] = a.ring_y[j];
+            S.up[r] = v.x;
+            S.upp[r] = v.y;
+            S.kp[r] = k.x;
+            if (SPIN) {
+                S.um[r] = v.z;
+                S.ump[r] = v.w;
+                S.km[r] = k.y;
+            } else {
+                S.um[r] = v.x;
+                S.km[r] = k.x;
+            }
+        }
+    }
+}
+
 template <int R, bool SPIN> __device__ inline bool leg_any_scaled(const LegState<R, SPIN> &S) {
     bool sc = false;
 #pragma unroll
@@ -270,19 +303,24 @@ __device__ inline void synth_clear_scaled(const LegState<R, SPIN> &S, double *fp
 }
 
 // One work item of the synthesis with R rings per lane (the item holds at
-// most 64 R rings).
+// most 64 R rings): the sums over the degrees l0 .. lmax of order m, where the
+// recurrence starts from the seed at l0 = max(m, s) (soff < 0) or from the
+// states stored for l0 (soff >= 0, see leg_init_stored), written to the F
+// layout at Fout.
 template <int R, bool SPIN>
-__device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, double4 (*sbuf)[2][kStage + 1]) {
+__device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, int l0, int lmax, int64_t soff,
+                                      const double4 *st_mu, const int2 *st_k, double *Fout,
+                                      double4 (*sbuf)[2][kStage + 1]) {
     const int m = it.m, s = a.spin, lane = threadIdx.x;
-    const int l0 = m > s ? m : s, lmax = a.lmax;
     if (l0 > lmax) return;
 
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const int64_t base = (int64_t)m * (2 * a.lmax + 1 - m) / 2;
     const double4 *T4 = a.coef + base;
     sbuf[0][lane >> 5][lane & 31] = stage_entry_synth(a, T4, base, m, l0, lmax, lane);
 
     LegState<R, SPIN> S;
-    leg_init<R, SPIN>(a, it, lane, S);
+    if (soff < 0) leg_init<R, SPIN>(a, it, lane, S);
+    else leg_init_stored<R, SPIN>(a, m, it.jb, it.je, lane, st_mu, st_k, soff, S);
     double fpr[R], fpi[R], fmr[R], fmi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) fpr[r] = fpi[r] = fmr[r] = fmi[r] = 0.0;
@@ -366,8 +404,8 @@ __device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, doubl
 
     synth_clear_scaled<R, SPIN>(S, fpr, fpi, fmr, fmi);
     const double sgn_neg = (s & 1) ? 1.0 : -1.0;  // -(-1)^s
-    double2 *Fp = reinterpret_cast<double2 *>(a.F) + (int64_t)(a.mmax + m) * a.nring;
-    double2 *Fm = reinterpret_cast<double2 *>(a.F) + (int64_t)(a.mmax - m) * a.nring;
+    double2 *Fp = reinterpret_cast<double2 *>(Fout) + (int64_t)(a.mmax + m) * a.nring;
+    double2 *Fm = reinterpret_cast<double2 *>(Fout) + (int64_t)(a.mmax - m) * a.nring;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!S.act[r]) continue;
@@ -386,8 +424,65 @@ __global__ __launch_bounds__(64) void k_leg_synth(LegArgs a) {
     if (idx >= a.nitems) return;
     const LegItem it = a.items[idx];
     if (it.je <= it.jb) return;
-    if (R > 1 && it.je - it.jb <= 64) leg_synth_item<1, SPIN>(a, it, sbuf);
-    else leg_synth_item<R, SPIN>(a, it, sbuf);
+    const int l0 = it.m > a.spin ? it.m : a.spin;
+    if (R > 1 && it.je - it.jb <= 64)
+        leg_synth_item<1, SPIN>(a, it, l0, a.lmax, -1, nullptr, nullptr, a.F, sbuf);
+    else
+        leg_synth_item<R, SPIN>(a, it, l0, a.lmax, -1, nullptr, nullptr, a.F, sbuf);
+}
+
+// Degree-segmented synthesis (plans whose items would not fill the GPU): an
+// item sums the degrees [la, lb) of its order, starting from the recurrence
+// state stored at plan time for la (every segment start is one of the
+// adjoint's), into F (segment 0) or into the partial copy of F of its segment
+// (segment k >= 1 at parts + (k - 1) part_stride doubles); k_synth_parts_sum
+// then adds the partials into F.
+struct SynSegArgs {
+    LegArgs a;
+    const SynSegItem *items;
+    int nitems;
+    const double4 *st_mu;
+    const int2 *st_k;
+    double *parts;
+    int64_t part_stride;
+};
+
+template <int R, bool SPIN>
+__global__ __launch_bounds__(64) void k_leg_synth_seg(SynSegArgs A) {
+    __shared__ double4 sbuf[2][2][kStage + 1];
+    if ((int)blockIdx.x >= A.nitems) return;
+    const SynSegItem q = A.items[blockIdx.x];
+    if (q.je <= q.jb) return;
+    const LegItem it{q.m, q.jb, q.je};
+    double *F = q.part == 0 ? A.a.F : A.parts + (int64_t)(q.part - 1) * A.part_stride;
+    if (R > 1 && q.je - q.jb <= 64)
+        leg_synth_item<1, SPIN>(A.a, it, q.la, q.lb - 1, q.soff, A.st_mu, A.st_k, F, sbuf);
+    else
+        leg_synth_item<R, SPIN>(A.a, it, q.la, q.lb - 1, q.soff, A.st_mu, A.st_k, F, sbuf);
+}
+
+// F(m)[j] += the partials of segments 1 .. nseg_m - 1 for every written entry
+// (|m| <= ring_mmax[j] and order |m| has degrees), nseg_m = ceil((lmax + 1 -
+// max(|m|, s)) / S); one thread per entry of F, rings contiguous.
+__global__ __launch_bounds__(256) void k_synth_parts_sum(double2 *F, const double2 *parts, int64_t part_stride,
+                                                         const int32_t *ring_mmax, int nring, int mmax, int lmax,
+                                                         int spin, int S) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)(2 * mmax + 1) * nring;
+    if (e >= n) return;
+    const int mi = (int)(e / nring), j = (int)(e - (int64_t)mi * nring);
+    const int m = mi >= mmax ? mi - mmax : mmax - mi;
+    const int l0 = m > spin ? m : spin;
+    if (l0 > lmax || ring_mmax[j] < m) return;
+    const int nseg = (lmax + 1 - l0 + S - 1) / S;
+    if (nseg < 2) return;
+    double2 acc = F[e];
+    for (int k = 1; k < nseg; ++k) {
+        const double2 v = parts[(int64_t)(k - 1) * part_stride + e];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    F[e] = acc;
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -495,37 +590,12 @@ struct AdjArgs {
 // Rings [j0 + 64 r + lane] of order m: seeds (first segment) or the stored states.
 template <int R, bool SPIN>
 __device__ inline void adj_seg_init(const AdjArgs &A, const AdjItem &it, int j0, int lane, LegState<R, SPIN> &S) {
-    const LegArgs &a = A.a;
     if (it.soff < 0) {
         const LegItem li{it.m, j0, it.je};
-        leg_init<R, SPIN>(a, li, lane, S);
+        leg_init<R, SPIN>(A.a, li, lane, S);
         return;
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int j = j0 + r * 64 + lane;
-        S.act[r] = (j < it.je) && (a.ring_mmax[j] >= it.m);
-        S.y[r] = 0.0;
-        S.up[r] = S.upp[r] = S.um[r] = S.ump[r] = 0.0;
-        S.kp[r] = S.km[r] = 0;
-        if (S.act[r]) {
-            const int64_t q = it.soff + (j - it.jb);
-            const double4 v = A.st_mu[q];
-            const int2 k = A.st_k[q];
-            S.y[r] = a.ring_y[j];
-            S.up[r] = v.x;
-            S.upp[r] = v.y;
-            S.kp[r] = k.x;
-            if (SPIN) {
-                S.um[r] = v.z;
-                S.ump[r] = v.w;
-                S.km[r] = k.y;
-            } else {
-                S.um[r] = v.x;
-                S.km[r] = k.x;
-            }
-        }
-    }
+    leg_init_stored<R, SPIN>(A.a, it.m, j0, it.je, lane, A.st_mu, A.st_k, it.soff + (j0 - it.jb), S);
 }
 
 // Zero outputs of order m for l in [l_from, l_to) (wave 0's lanes).
@@ -975,6 +1045,37 @@ hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, do
         case 8: leg_synth_r<8>(p, alm, F, mscale, st); break;
         default: leg_synth_r<4>(p, alm, F, mscale, st); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_synth_parts(const psht_plan_s &p, const void *alm, double *F, double *parts,
+                                  int64_t part_stride, double mscale, hipStream_t st) {
+    if (p.syn_seg == 0) return launch_leg_synth(p, alm, F, mscale, st);
+    if (p.n_syn_items == 0) return hipSuccess;
+    SynSegArgs A;
+    A.a = leg_args<1>(p, alm, nullptr, F);
+    A.a.mscale = mscale;
+    A.items = p.d_syn_items;
+    A.nitems = p.n_syn_items;
+    A.st_mu = reinterpret_cast<const double4 *>(p.d_adj_mu);
+    A.st_k = reinterpret_cast<const int2 *>(p.d_adj_k);
+    A.parts = parts;
+    A.part_stride = part_stride;
+    const dim3 grid(p.n_syn_items), block(64);
+    const bool two = p.syn_r == 2;
+    if (p.g.spin) {
+        if (two) hipLaunchKernelGGL((k_leg_synth_seg<2, true>), grid, block, 0, st, A);
+        else hipLaunchKernelGGL((k_leg_synth_seg<1, true>), grid, block, 0, st, A);
+    } else {
+        if (two) hipLaunchKernelGGL((k_leg_synth_seg<2, false>), grid, block, 0, st, A);
+        else hipLaunchKernelGGL((k_leg_synth_seg<1, false>), grid, block, 0, st, A);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || p.syn_parts == 0) return e;
+    const int64_t n = (int64_t)(2 * p.g.mmax + 1) * p.g.nring;
+    hipLaunchKernelGGL(k_synth_parts_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<double2 *>(F), reinterpret_cast<const double2 *>(parts), part_stride / 2,
+                       p.d_ring_mmax, p.g.nring, p.g.mmax, p.g.lmax, p.g.spin, p.syn_seg);
     return hipGetLastError();
 }
 

@@ -128,6 +128,17 @@ struct StateItem {
     int64_t soff;
 };
 
+// Work item of the degree-segmented synthesis: rings [jb, je) of order m
+// (at most 64 R), degrees [la, lb), starting from the seed (soff = -1, la =
+// max(m, s)) or from the adjoint's stored state of the item's first ring at
+// index soff; written to F (part 0) or to the partial copy `part` of F.
+struct SynSegItem {
+    int32_t m, jb, je;
+    int32_t la, lb;
+    int32_t part;
+    int64_t soff;
+};
+
 // ------------------------------------------------------------------- plan
 
 struct FftTable {
@@ -159,6 +170,13 @@ struct psht_plan_s {
     int32_t *d_adj_k = nullptr;    // [state] {k+, k-}
     int64_t n_adj_states = 0;
     int64_t alm_tail = 0;          // first coefficient index of order mmax + 1 (outputs zero from there)
+    // degree-segmented synthesis (plans whose synthesis items would not fill
+    // the GPU): items, segment length and number of partial copies of F
+    psht::SynSegItem *d_syn_items = nullptr;
+    int n_syn_items = 0;
+    int syn_seg = 0;    // 0: not segmented
+    int syn_parts = 0;  // partial copies of F (segments beyond the first of the longest order)
+    int syn_r = 2;      // rings per lane of the segmented items (1 or 2)
     psht::LegItem *d_leg_items64 = nullptr;  // 64-ring chunks (batched-maps kernel)
     int n_leg_items64 = 0;
     std::shared_ptr<psht::LegTable> leg;
@@ -193,6 +211,12 @@ namespace psht {
 // `mscale` multiplies the coefficients (synthesis) or the outputs (adjoint) of
 // every order m >= 1; 1 for the plain transforms.
 hipError_t launch_leg_synth(const psht_plan_s &p, const void *alm, double *F, double mscale, hipStream_t st);
+// The same through the degree-segmented work list when the plan has one
+// (syn_seg > 0), with the partial copies of F at `parts` (syn_parts copies of
+// 2 mmax + 1 by nring complex values, `part_stride` doubles apart); otherwise
+// launch_leg_synth.
+hipError_t launch_leg_synth_parts(const psht_plan_s &p, const void *alm, double *F, double *parts,
+                                  int64_t part_stride, double mscale, hipStream_t st);
 hipError_t launch_leg_adjoint(const psht_plan_s &p, const double *F, void *alm, double mscale, hipStream_t st);
 constexpr int kAdjMaxWavesHost = 4;  // waves per workgroup of the segmented adjoint
 constexpr int kAdjMaxRings = 6;      // rings per lane of the segmented adjoint

@@ -204,10 +204,13 @@ class Plan:
             _lib.check(_lib.load().psht_stage(self._h, stage, inp.data_ptr(), out.data_ptr(), _stream(stream)))
         return out
 
-    def legendre_synth(self, alm: torch.Tensor) -> torch.Tensor:
-        """Per-ring Fourier coefficients F_m(theta_j), shape (2 mmax + 1, Lmax + 1)."""
+    def legendre_synth(self, alm: torch.Tensor, workspace: bool = False) -> torch.Tensor:
+        """Per-ring Fourier coefficients F_m(theta_j), shape (2 mmax + 1, Lmax + 1).  With workspace=True
+        through the work decomposition of synth (degree segments when info["syn_segment"] is non-zero)."""
         out = torch.empty((2 * self.info["mmax"] + 1, self.info["Lmax"] + 1), dtype=torch.complex128,
                           device=self.device)
+        if workspace:
+            return self._stage_ws(_lib.STAGE_LEGENDRE_SYNTH, alm.contiguous(), out)
         return self.stage(_lib.STAGE_LEGENDRE_SYNTH, alm.contiguous(), out)
 
     def legendre_adjoint(self, F: torch.Tensor) -> torch.Tensor:

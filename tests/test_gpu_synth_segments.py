@@ -1,0 +1,175 @@
+"""Degree-segmented Legendre synthesis.
+
+A plan whose per-order synthesis items would leave most of the GPU idle (a
+small cap at high lmax: few orders, each with thousands of sequential
+recurrence steps) cuts every order's degrees into segments that start from
+the recurrence states the plan stores for the adjoint, and adds the partial
+ring coefficients of the segments into F.  Checked against the oracle (maps
+and ring coefficients of Sec. I), against the same plan built without
+segments, and for the exact transpose with the adjoint.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2603_17166_amd import synthetic as syn
+from paper_2603_17166_amd.plan import Plan
+
+pytestmark = pytest.mark.gpu
+DEG = math.pi / 180
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.as_tensor(x).cuda()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# lmax, spin, cap radius (deg), points, oracle points, eps, precision, forced segment length (None: the plan's)
+CASES = [
+    (1024, 2, 2.0, 4000, 300, 1e-10, "fp64", None),
+    (512, 0, 5.0, 4000, 400, 1e-10, "fp64", None),
+    (700, 1, 3.0, 3000, 300, 1e-8, "fp64", 64),     # odd spin, the shortest segments
+    (1024, 3, 1.0, 3000, 300, 1e-12, "fp64", 128),
+    (1024, 2, 2.0, 4000, 300, 1e-5, "fp32", None),
+    (4096, 2, 2.0, 20000, 60, 1e-10, "fp64", None),  # deep polar: states stored while still scaled
+]
+
+
+def _ids(c):
+    return "l%d-s%d-r%g-%s-eps%g-seg%s" % (c[0], c[1], c[2], c[6], c[5], c[7])
+
+
+def _plan(th, ph, lmax, spin, eps, prec, seg, monkeypatch):
+    if seg is None:
+        monkeypatch.delenv("PSHT_SYN_SEG", raising=False)
+    else:
+        monkeypatch.setenv("PSHT_SYN_SEG", str(seg))
+    p = Plan(th, ph, lmax, spin, eps, prec)
+    monkeypatch.setenv("PSHT_SYN_SEG", "0")
+    plain = Plan(th, ph, lmax, spin, eps, prec)
+    monkeypatch.delenv("PSHT_SYN_SEG", raising=False)
+    return p, plain
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_segmented_synth(case, monkeypatch):
+    lmax, spin, rad, n, nref, eps, prec, seg = case
+    say("segmented synthesis", _ids(case))
+    th, ph = syn.uniform_cap(n, rad * DEG, 12000 + lmax + spin)
+    a = syn.gaussian_alm(lmax, spin, 12100 + spin)
+    p, plain = _plan(th, ph, lmax, spin, eps, prec, seg, monkeypatch)
+    info = p.info
+    say("  syn_segment %d, syn_parts %d, adj_segment %d, mmax %d, Lmax %d" %
+        (info["syn_segment"], info["syn_parts"], info["adj_segment"], info["mmax"], info["Lmax"]))
+    assert info["syn_segment"] > 0 and info["syn_parts"] >= 1
+    assert info["syn_segment"] % info["adj_segment"] == 0
+    if seg is not None:
+        assert info["syn_segment"] == seg
+    assert plain.info["syn_segment"] == 0 and plain.info["syn_parts"] == 0
+    # the partial copies of F fit the workspace
+    fbytes = (2 * info["mmax"] + 1) * (info["Lmax"] + 1) * 16
+    assert info["workspace_bytes_per_map"] >= (1 + info["syn_parts"]) * fbytes
+
+    ad = dev(a)
+    f = p.synth(ad).cpu().numpy().astype(np.complex128)
+    f0 = plain.synth(ad).cpu().numpy().astype(np.complex128)
+    idx = np.sort(syn.rng(12200).choice(n, nref, replace=False))
+    ref = oracle.synth(a, th[idx], ph[idx], lmax, spin)
+    err = rel_l2(f[idx], ref)
+    d = rel_l2(f, f0)
+    say("  vs oracle %.3e, vs unsegmented %.3e" % (err, d))
+    assert err <= 10 * eps
+    # the same sums in another order: FP64 rounding (FP32 maps: one FP32 rounding)
+    assert d <= (2e-6 if prec == "fp32" else 1e-12)
+    p.close()
+    plain.close()
+
+
+@pytest.mark.parametrize("lmax,spin,rad,seg", [(512, 2, 3.0, None), (700, 1, 2.0, 64), (2048, 0, 1.0, None),
+                                               (4096, 2, 2.0, None)])
+def test_segmented_legendre_stage(lmax, spin, rad, seg, monkeypatch):
+    """F of the segmented work list against the oracle's ring coefficients and
+    against the plain work list of the same plan."""
+    say("segmented Legendre stage", lmax, spin, rad, seg)
+    th, ph = syn.uniform_cap(500, rad * DEG, 12300 + lmax)
+    p, plain = _plan(th, ph, lmax, spin, 1e-10, "fp64", seg, monkeypatch)
+    assert p.info["syn_segment"] > 0
+    a = syn.gaussian_alm(lmax, spin, 12400 + spin)
+    ad = dev(a)
+    F = p.legendre_synth(ad, workspace=True).cpu().numpy()
+    F0 = p.legendre_synth(ad).cpu().numpy()  # without a workspace: the plain work list
+    L, mmax = p.info["Lmax"], p.info["mmax"]
+    thj = 2 * math.pi * np.arange(L + 1) / p.info["n2"] * p.info["theta_max"] / math.pi
+    # the oracle on every fourth ring (its cost grows with lmax^2 per ring)
+    rows = np.arange(0, L + 1, 4 if lmax > 1000 else 1)
+    ref = oracle.ring_coeffs(a, thj[rows], lmax, spin, mmax)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(F[:, rows] - ref)) / scale
+    d = np.max(np.abs(F - F0)) / scale
+    say("  vs oracle %.3e, vs plain work list %.3e" % (err, d))
+    # FP64 rounding of the recurrence grows with the number of steps: a few
+    # units of roundoff per degree (1.4e-12 at lmax 4096, for both work lists)
+    assert err < max(1e-12, 1e-15 * lmax)
+    assert d < 1e-13
+    # the entries above a ring's cut-off stay zero (an entry whose terms all
+    # stay below the scaled range may be zero in one list and negligibly small,
+    # below 2^-800 of the largest, in the other)
+    assert np.all(np.abs(F[F0 == 0]) <= 1e-240 * scale) and np.all(np.abs(F0[F == 0]) <= 1e-240 * scale)
+    p.close()
+    plain.close()
+
+
+@pytest.mark.parametrize("lmax,spin,prec,eps", [(1024, 2, "fp64", 1e-10), (1024, 0, "fp32", 1e-5)])
+def test_segmented_dot_product(lmax, spin, prec, eps):
+    """<synth a, f> = <a, adjoint f> on a segmented plan."""
+    say("segmented dot", lmax, spin, prec)
+    n = 3000
+    th, ph = syn.uniform_cap(n, 2.5 * DEG, 12500)
+    p = Plan(th, ph, lmax, spin, eps, prec)
+    assert p.info["syn_segment"] > 0
+    fp32 = bool(p.info["map_is_fp32"])
+    a = syn.gaussian_alm(lmax, spin, 12600)
+    f = syn.gaussian_map(n, 12700).astype(np.complex64 if fp32 else np.complex128)
+    sa = p.synth(dev(a)).cpu().numpy().astype(np.complex128)
+    at = p.adjoint(dev(f)).cpu().numpy()
+    lhs = oracle.map_dot(sa, f.astype(np.complex128))
+    rhs = oracle.alm_dot(a, at, lmax)
+    scale = np.linalg.norm(sa) * np.linalg.norm(f)
+    say("  |lhs-rhs|/scale = %.3e" % (abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= (2e-6 if fp32 else 1e-12) * scale
+    p.close()
+
+
+def test_segmented_multi_map_and_gradient_form(monkeypatch):
+    """Two maps per call (below the batching threshold: the segmented list per
+    map) against one-map calls, and the gradient form (inputs of orders m >= 1
+    scaled) against the plain work list."""
+    lmax, spin = 1024, 2
+    th, ph = syn.uniform_cap(3000, 2.0 * DEG, 12800)
+    p, plain = _plan(th, ph, lmax, spin, 1e-10, "fp64", None, monkeypatch)
+    assert p.info["syn_segment"] > 0
+    a = np.stack([syn.gaussian_alm(lmax, spin, 12900 + k) for k in range(2)])
+    both = p.synth(dev(a)).cpu().numpy()
+    for k in range(2):
+        one = p.synth(dev(a[k])).cpu().numpy()
+        assert np.array_equal(both[k], one)
+    g = p.synth_grad(dev(a)).cpu().numpy()
+    g0 = plain.synth_grad(dev(a)).cpu().numpy()
+    d = rel_l2(g, g0)
+    say("  gradient form vs plain work list %.3e" % d)
+    assert d <= 1e-12
+    p.close()
+    plain.close()
