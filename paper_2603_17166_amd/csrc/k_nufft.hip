@@ -18,6 +18,8 @@
 // LDS: interpolation reads it once from HBM; spreading accumulates into it
 // (in double) with LDS atomics and flushes it with one global atomic per
 // non-zero cell and component.
+#include <cstdlib>
+
 #include "nufft_index.h"
 #include "psht_internal.h"
 
@@ -39,6 +41,7 @@ struct NufftArgs {
     // points whose stencil left their tile (never expected: the plan verifies
     // the sort; counted, not silently skipped)
     unsigned long long *dropped;
+    int xcd_group;  // tiles per XCD group (xcd_tile)
 };
 
 // Row stride (in elements) of a tile's subgrid in LDS: odd, so that the
@@ -68,23 +71,6 @@ __device__ inline double es_exp(double x) {
     return ldexp(p, (int)n);
 }
 
-// The same in float for the FP32 form: degree 7 (truncation below 5e-9
-// relative, under float rounding); the FP32 kernel exponent lies in
-// [-beta, 0] with beta <= 17 (W <= 7).
-__device__ inline float es_expf(float x) {
-    const float n = rintf(x * 1.44269504f);
-    const float r = fmaf(-n, 0.693147182f, x);
-    float p = 1.0f / 5040.0f;
-    p = fmaf(p, r, 1.0f / 720.0f);
-    p = fmaf(p, r, 1.0f / 120.0f);
-    p = fmaf(p, r, 1.0f / 24.0f);
-    p = fmaf(p, r, 1.0f / 6.0f);
-    p = fmaf(p, r, 0.5f);
-    p = fmaf(p, r, 1.0f);
-    p = fmaf(p, r, 1.0f);
-    return ldexpf(p, (int)n);
-}
-
 // ES kernel psi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| <= 1, used for the
 // two edge taps (at most about 2e-5 at W = 11, larger for small W, where the
 // tolerance is correspondingly looser): the error of the exponential stays
@@ -93,9 +79,16 @@ __device__ inline double es_kernel(double z, double beta) {
     double t = fmax(0.0, 1.0 - z * z);
     return es_exp(beta * (sqrt(t) - 1.0));
 }
+// FP32 form: the hardware square root and base-2 exponential (v_sqrt_f32,
+// v_exp_f32, about one ulp each).  The exponent, at most beta log2(e) in
+// magnitude, then carries an absolute error of a few ulp of that bound (about
+// 3e-6 at W = 6, 1e-5 at W = 16), which is the relative error of the tap.  An
+// edge tap weighs at most psi((W - 2)/W), 3 % of the peak at W = 6 and far less
+// for wider kernels, so the sum moves by less than 1e-7 relative: below the
+// rounding of the FP32 grid itself.
 __device__ inline float es_kernel(float z, float beta) {
-    float t = fmaxf(0.0f, 1.0f - z * z);
-    return es_expf(beta * (sqrtf(t) - 1.0f));
+    const float t = fmaxf(0.0f, 1.0f - z * z);
+    return __builtin_amdgcn_exp2f(beta * 1.44269504f * (__builtin_amdgcn_sqrtf(t) - 1.0f));
 }
 
 // Kernel weights of the W taps of a point with grid coordinate X and stencil
@@ -164,6 +157,66 @@ __device__ inline void es_weights_n(const double *X, const int *a0, T beta, Unif
     }
 }
 
+// Cell (i, j) = (e / SY, e mod SY) of the flat subgrid index e = threadIdx.x +
+// k kTileThreads, advanced by one stride at a time: one division per thread
+// instead of one per cell.
+struct SubgridWalk {
+    int i, j, di, dj;
+    __device__ explicit SubgridWalk(int SY) {
+        i = (int)threadIdx.x / SY;
+        j = (int)threadIdx.x - i * SY;
+        di = kTileThreads / SY;
+        dj = kTileThreads - di * SY;
+    }
+    __device__ void next(int SY) {
+        i += di;
+        j += dj;
+        if (j >= SY) {
+            j -= SY;
+            ++i;
+        }
+    }
+};
+
+// Column c0 + j of a tile's subgrid (c0 < Nphi, j < SY) reduced mod Nphi: the
+// subgrid may wrap more than once when Nphi is small.
+__device__ inline int wrap_subgrid_col(int c, int Nphi) {
+    while (c >= Nphi) c -= Nphi;
+    return c;
+}
+
+// Block -> tile map for the interpolation and spreading launches (grid of
+// xcd_tile_blocks blocks).  Blocks are dealt round-robin to the eight XCDs,
+// each with its own L2.  Groups of G consecutive tiles (adjacent in phi) go
+// to one XCD and the groups rotate over the XCDs: neighbours inside a group
+// share an L2 (their overlapping subgrid halos and the map's cache lines that
+// straddle two tiles), while the rotation keeps the XCDs' loads even.  G = 1
+// is the plain round-robin.  Returns -1 past the end.
+__device__ inline int xcd_tile(int bid, int ntiles, int G) {
+    const int x = bid & 7, k = bid >> 3;
+    const int q = k / G;
+    const int t = (q * 8 + x) * G + (k - q * G);
+    return t < ntiles ? t : -1;
+}
+__host__ inline unsigned xcd_tile_blocks(int ntiles, int G) {
+    return 8u * (unsigned)G * (unsigned)((ntiles + 8 * G - 1) / (8 * G));
+}
+// Tiles per group: the largest power of two up to 64 that leaves at least 64
+// groups per XCD (small plans keep the plain round-robin).  lmax 4096, FP32:
+// interpolation 0.313 -> 0.299 ms at G = 64, spreading within 2 %.
+// PSHT_XCD_GROUP fixes it for tuning runs.
+static int xcd_group(int ntiles) {
+    static const int forced = [] {
+        const char *e = getenv("PSHT_XCD_GROUP");
+        const int v = e ? atoi(e) : 0;
+        return v >= 1 && v <= 4096 ? v : 0;
+    }();
+    if (forced) return forced;
+    int G = 1;
+    while (G < 64 && (int64_t)ntiles >= (int64_t)2 * G * 8 * 64) G *= 2;
+    return G;
+}
+
 template <typename T> __device__ inline const T *table(const NufftArgs &a);
 template <> __device__ inline const double *table<double>(const NufftArgs &a) { return a.poly; }
 template <> __device__ inline const float *table<float>(const NufftArgs &a) { return a.poly32; }
@@ -180,20 +233,22 @@ __global__ __launch_bounds__(kTileThreads) void k_interp(NufftArgs a, const type
     extern __shared__ __align__(16) unsigned char smem[];
     C *S = reinterpret_cast<C *>(smem);
     const UniformPtr<T> sC = uniform_ptr(table<T>(a));
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, a.ntx * a.nty, a.xcd_group);
+    if (t < 0) return;
     const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
     if (p0 == p1) return;
     const int tx = t / a.nty, ty = t - tx * a.nty;
     const int SX = a.tile_x + W - 1, SY = a.tile_y + W - 1, SYP = tile_row_stride(a.tile_y, W);
     const int r0 = tx * a.tile_x, c0 = ty * a.tile_y;
-    for (int e = threadIdx.x; e < SX * SY; e += kTileThreads) {
-        const int i = e / SY, j = e - i * SY;
-        const int row = r0 + i;
-        const int col = (c0 + j) % a.Nphi;  // the subgrid may wrap more than once when Nphi is small
-        C v;
-        v.x = v.y = (T)0;
-        if (row < a.rows_used) v = U[(int64_t)row * a.Nphi + col];
-        S[i * SYP + j] = v;
+    {
+        SubgridWalk w(SY);
+        for (int e = threadIdx.x; e < SX * SY; e += kTileThreads, w.next(SY)) {
+            const int row = r0 + w.i;
+            C v;
+            v.x = v.y = (T)0;
+            if (row < a.rows_used) v = U[(int64_t)row * a.Nphi + wrap_subgrid_col(c0 + w.j, a.Nphi)];
+            S[w.i * SYP + w.j] = v;
+        }
     }
     __syncthreads();
     // one entry per thread; the two entries of a slot (same cell) sit in
@@ -245,7 +300,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
                                                          T *U) {
     typedef typename CplxT<T>::type C;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, a.ntx * a.nty, a.xcd_group);
+    if (t < 0) return;
     const int p0 = a.tile_start[t], p1 = a.tile_start[t + 1];
     if (p0 == p1) return;
     const int tx = t / a.nty, ty = t - tx * a.nty;
@@ -300,14 +356,13 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(NufftArgs a, const type
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < SX * SY; e += kTileThreads) {
-        const int i = e / SY, j = e - i * SY;
-        const int row = r0 + i;
+    SubgridWalk w(SY);
+    for (int e = threadIdx.x; e < SX * SY; e += kTileThreads, w.next(SY)) {
+        const int row = r0 + w.i;
         if (row >= a.rows_used) continue;
-        const T vr = (T)Sre[i * SYP + j], vi = (T)Sim[i * SYP + j];
+        const T vr = (T)Sre[w.i * SYP + w.j], vi = (T)Sim[w.i * SYP + w.j];
         if (vr == (T)0 && vi == (T)0) continue;
-        const int col = (c0 + j) % a.Nphi;  // the subgrid may wrap more than once when Nphi is small
-        T *dst = U + 2 * ((int64_t)row * a.Nphi + col);
+        T *dst = U + 2 * ((int64_t)row * a.Nphi + wrap_subgrid_col(c0 + w.j, a.Nphi));
         atomicAdd(dst, vr);
         atomicAdd(dst + 1, vi);
     }
@@ -332,6 +387,7 @@ static NufftArgs nufft_args(const psht_plan_s &p) {
     a.poly32 = p.d_es_poly32;
     a.geo = tile_geom(p);
     a.dropped = p.d_dropped;
+    a.xcd_group = xcd_group(p.ntiles);
     return a;
 }
 
@@ -340,7 +396,7 @@ static hipError_t launch_interp_w(const psht_plan_s &p, const void *U, void *map
     typedef typename CplxT<T>::type C;
     NufftArgs a = nufft_args(p);
     size_t lds = (size_t)(p.tile_x + W - 1) * tile_row_stride(p.tile_y, W) * sizeof(C);
-    hipLaunchKernelGGL((k_interp<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
+    hipLaunchKernelGGL((k_interp<T, W>), dim3(xcd_tile_blocks(p.ntiles, a.xcd_group)), dim3(kTileThreads), lds, st, a,
                        static_cast<const C *>(U), static_cast<C *>(map));
     return hipGetLastError();
 }
@@ -350,7 +406,7 @@ static hipError_t launch_spread_w(const psht_plan_s &p, const void *map, void *U
     typedef typename CplxT<T>::type C;
     NufftArgs a = nufft_args(p);
     size_t lds = (size_t)(p.tile_x + W - 1) * tile_row_stride(p.tile_y, W) * 2 * sizeof(double);
-    hipLaunchKernelGGL((k_spread<T, W>), dim3(p.ntiles), dim3(kTileThreads), lds, st, a,
+    hipLaunchKernelGGL((k_spread<T, W>), dim3(xcd_tile_blocks(p.ntiles, a.xcd_group)), dim3(kTileThreads), lds, st, a,
                        static_cast<const C *>(map), static_cast<T *>(U));
     return hipGetLastError();
 }

@@ -36,8 +36,11 @@ PSHT_HD constexpr int es_poly_degree(int W, bool fp32) {
     return fp32 ? (W + 2 > 10 ? W + 2 : 10) : (W + 1 > 12 ? W + 1 : 12);
 }
 
-// b0 reduced to [0, Nphi).
+// b0 reduced to [0, Nphi).  A point's b0 lies in [-W/2, Nphi): a compare or
+// one add; the remainder only for other values.
 PSHT_HD inline int wrap_col(int b0, int Nphi) {
+    if (b0 >= 0 && b0 < Nphi) return b0;
+    if (b0 < 0 && b0 >= -Nphi) return b0 + Nphi;
     int b = b0 % Nphi;
     return b < 0 ? b + Nphi : b;
 }
