@@ -314,9 +314,26 @@ static void es_poly_table(Geometry &g) {
 
 // ---------------------------------------------------- polar cut-off search
 
+// Factors of the recurrence coefficients that depend on l alone, shared by
+// every order and ring of a cut-off search: (l+1) sqrt((2l+3)(2l+1)),
+// (l+1) sqrt((2l+3)/(2l-1)) / l and 1 / (l(l+1)).
+struct DegreeRoots {
+    std::vector<ld> r1, r2, il;
+    explicit DegreeRoots(int lmax) : r1(lmax + 1), r2(lmax + 1), il(lmax + 1) {
+        for (int l = 0; l <= lmax; ++l) {
+            const ld L = l;
+            r1[l] = (L + 1) * sqrtl((2 * L + 3) * (2 * L + 1));
+            r2[l] = l > 0 ? (L + 1) * sqrtl((2 * L + 3) / (2 * L - 1)) / L : 0;
+            il[l] = l > 0 ? 1 / (L * (L + 1)) : 0;
+        }
+    }
+};
+
 // Is max over l <= lmax of max(|lambda+_lm(theta)|, |lambda-_lm(theta)|) >= tau?
 // Long double recurrence, seeds in log space (independent of the GPU seeds).
-static bool leg_significant(int lmax, int s, int m, ld theta, ld tau) {
+// The root sqrt((l^2 - m^2)(l^2 - s^2)) of a step's c is the previous step's
+// D, so each step takes one square root and one division.
+static bool leg_significant(int lmax, int s, int m, ld theta, ld tau, const DegreeRoots &R) {
     int l0 = std::max(m, s);
     if (l0 > lmax) return false;
     ld ch = cosl(theta / 2), sh = sinl(theta / 2), x = cosl(theta);
@@ -339,16 +356,18 @@ static bool leg_significant(int lmax, int s, int m, ld theta, ld tau) {
     ld lp = seed(dms, m + s), lm = seed(m + s, dms);
     if (fabsl(lp) >= tau || fabsl(lm) >= tau) return true;
     if (lp == 0 && lm == 0 && sh != 0) return false;
-    ld lpp = 0, lmp = 0;
-    ld M = m, S = s;
+    ld lpp = 0, lmp = 0, Dprev = 0;
+    const ld M = m, S = s, MS = M * S;
     for (int l = l0; l < lmax; ++l) {
-        ld L = l;
-        ld D = sqrtl(((L + 1) * (L + 1) - M * M) * ((L + 1) * (L + 1) - S * S));
-        ld a = sqrtl((2 * L + 3) * (2 * L + 1)) * (L + 1) / D;
-        ld b = (m * s == 0) ? 0 : a * M * S / (L * (L + 1));
-        ld c = (l == l0) ? 0 : sqrtl((2 * L + 3) / (2 * L - 1)) * (L + 1) * sqrtl((L * L - M * M) * (L * L - S * S)) / (L * D);
-        ld np = (a * x + b) * lp - c * lpp;
-        ld nm = (a * x - b) * lm - c * lmp;
+        const ld L = l;
+        const ld D = sqrtl(((L + 1) * (L + 1) - M * M) * ((L + 1) * (L + 1) - S * S));
+        const ld iD = 1 / D;
+        const ld a = R.r1[l] * iD;
+        const ld b = (m * s == 0) ? 0 : a * MS * R.il[l];
+        const ld c = (l == l0) ? 0 : R.r2[l] * Dprev * iD;
+        Dprev = D;
+        const ld np = (a * x + b) * lp - c * lpp;
+        const ld nm = (a * x - b) * lm - c * lmp;
         lpp = lp;
         lp = np;
         lmp = lm;
@@ -360,17 +379,17 @@ static bool leg_significant(int lmax, int s, int m, ld theta, ld tau) {
 
 // Largest m with a significant ring contribution (polar optimization: orders
 // well above lmax sin(theta) are irrelevant on the ring, Sec. II.A).
-static int ring_cutoff(int lmax, int s, ld theta, ld tau) {
+static int ring_cutoff(int lmax, int s, ld theta, ld tau, const DegreeRoots &R) {
     if (theta == 0) return std::min(s, lmax);
     int lo = (int)floorl(lmax * sinl(theta));
     lo = std::max(0, std::min(lo, lmax));
-    while (lo > 0 && !leg_significant(lmax, s, lo, theta, tau)) lo /= 2;
-    if (!leg_significant(lmax, s, lo, theta, tau)) return std::min(s, lmax);
-    if (leg_significant(lmax, s, lmax, theta, tau)) return lmax;
+    while (lo > 0 && !leg_significant(lmax, s, lo, theta, tau, R)) lo /= 2;
+    if (!leg_significant(lmax, s, lo, theta, tau, R)) return std::min(s, lmax);
+    if (leg_significant(lmax, s, lmax, theta, tau, R)) return lmax;
     int hi = lmax;  // lo significant, hi not
     while (hi - lo > 1) {
         int mid = lo + (hi - lo) / 2;
-        if (leg_significant(lmax, s, mid, theta, tau))
+        if (leg_significant(lmax, s, mid, theta, tau, R))
             lo = mid;
         else
             hi = mid;
@@ -660,12 +679,13 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
     g.ring_mmax.assign(g.nring, lmax);
     if (with_cutoffs) {
         ld tau = (ld)(kPolarTauRel * eps);
+        const DegreeRoots roots(lmax);
         unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         std::vector<std::thread> th;
         for (unsigned t = 0; t < nt; ++t)
             th.emplace_back([&, t]() {
                 for (int j = (int)t; j < g.nring; j += (int)nt)
-                    g.ring_mmax[j] = ring_cutoff(lmax, spin, (ld)g.ring_theta[j], tau);
+                    g.ring_mmax[j] = ring_cutoff(lmax, spin, (ld)g.ring_theta[j], tau, roots);
             });
         for (auto &x : th) x.join();
     }
@@ -747,34 +767,50 @@ void leg_table_host(LegTable &t, int lmax, int s) {
     t.h_coef.assign(4 * nalm, 0.0);
     t.h_kmant.assign(lmax + 1, 0.0);
     t.h_kexp.assign(lmax + 1, 0);
-    std::vector<ld> a(lmax + 2), b(lmax + 2), c(lmax + 2), P(lmax + 2);
-    ld S = s;
-    ld binom_mant = 0.5L;  // C(2m, m+s) = binom_mant * 2^binom_exp for the current m >= s
-    int binom_exp = 1;
-    for (int m = 0; m <= lmax; ++m) {
-        int l0 = std::max(m, s);
-        if (m > s) {
-            int e;
-            binom_mant = frexpl(binom_mant * ((ld)(2 * m) * (2 * m - 1) / ((ld)(m + s) * (m - s))), &e);
-            binom_exp += e;
+    // C(2m, m+s) = binom_mant[m] * 2^binom_exp[m] for m >= s, by the running
+    // product over m (the one part that is sequential in m)
+    std::vector<ld> binom_mant(lmax + 1, 0.5L);
+    std::vector<int> binom_exp(lmax + 1, 1);
+    {
+        ld bm = 0.5L;
+        int be = 1;
+        for (int m = 0; m <= lmax; ++m) {
+            if (m > s) {
+                int e;
+                bm = frexpl(bm * ((ld)(2 * m) * (2 * m - 1) / ((ld)(m + s) * (m - s))), &e);
+                be += e;
+            }
+            binom_mant[m] = bm;
+            binom_exp[m] = be;
         }
-        if (l0 > lmax) continue;
-        ld M = m;
+    }
+    const DegreeRoots R(lmax);
+    const ld S = s;
+    // one order m: the recurrence coefficients a, b, c (one square root per
+    // degree: the root in c is the previous degree's D), the normalisation P
+    // and the seed factor K_m
+    auto order = [&](int m, std::vector<ld> &a, std::vector<ld> &b, std::vector<ld> &c, std::vector<ld> &P) {
+        const int l0 = std::max(m, s);
+        if (l0 > lmax) return;
+        const ld M = m;
+        ld Dprev = 0;
         for (int l = l0; l <= lmax; ++l) {
-            ld L = l;
-            ld D = sqrtl(((L + 1) * (L + 1) - M * M) * ((L + 1) * (L + 1) - S * S));
-            a[l] = sqrtl((2 * L + 3) * (2 * L + 1)) * (L + 1) / D;
-            b[l] = (m * s == 0) ? 0 : a[l] * M * S / (L * (L + 1));
-            c[l] = (l == l0) ? 0 : sqrtl((2 * L + 3) / (2 * L - 1)) * (L + 1) * sqrtl((L * L - M * M) * (L * L - S * S)) / (L * D);
+            const ld L = l;
+            const ld D = sqrtl(((L + 1) * (L + 1) - M * M) * ((L + 1) * (L + 1) - S * S));
+            const ld iD = 1 / D;
+            a[l] = R.r1[l] * iD;
+            b[l] = (m * s == 0) ? 0 : a[l] * M * S * R.il[l];
+            c[l] = (l == l0) ? 0 : R.r2[l] * Dprev * iD;
+            Dprev = D;
         }
         P[l0] = 1;
         if (l0 + 1 <= lmax) P[l0 + 1] = 1;
         for (int l = l0 + 1; l < lmax; ++l) P[l + 1] = c[l] * P[l - 1];
-        int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+        const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
         for (int l = l0; l <= lmax; ++l) {
             double *e = &t.h_coef[4 * (base + l)];
             if (l < lmax) {
-                ld A = a[l] * P[l] / P[l + 1], B = b[l] * P[l] / P[l + 1];
+                const ld A = a[l] * P[l] / P[l + 1], B = b[l] * P[l] / P[l + 1];
                 e[0] = (double)(-A);
                 e[1] = (double)(A + B);
                 e[2] = (double)(A - B);
@@ -785,8 +821,8 @@ void leg_table_host(LegTable &t, int lmax, int s) {
         int e2;
         ld mant;
         if (m >= s) {
-            mant = binom_mant;
-            e2 = binom_exp;
+            mant = binom_mant[m];
+            e2 = binom_exp[m];
         } else {
             mant = frexpl(expl(lgammal(2 * s + 1) - lgammal(s + m + 1) - lgammal(s - m + 1)), &e2);
         }
@@ -794,11 +830,25 @@ void leg_table_host(LegTable &t, int lmax, int s) {
             mant *= 2;
             e2 -= 1;
         }
-        ld K = sqrtl((2 * l0 + 1) / (4 * kPiL)) * sqrtl(mant);
+        const ld K = sqrtl((2 * l0 + 1) / (4 * kPiL)) * sqrtl(mant);
         int e3;
-        ld km = frexpl(K, &e3);
+        const ld km = frexpl(K, &e3);
         t.h_kmant[m] = (double)km;
         t.h_kexp[m] = e3 + e2 / 2;
+    };
+    // the orders are independent: host threads take them in turn (the work of
+    // order m falls with m, so interleaving keeps the threads even)
+    const unsigned nt = lmax < 64 ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto worker = [&](unsigned tid) {
+        std::vector<ld> a(lmax + 2), b(lmax + 2), c(lmax + 2), P(lmax + 2);
+        for (int m = (int)tid; m <= lmax; m += (int)nt) order(m, a, b, c, P);
+    };
+    if (nt == 1) {
+        worker(0);
+    } else {
+        std::vector<std::thread> th;
+        for (unsigned q = 0; q < nt; ++q) th.emplace_back(worker, q);
+        for (auto &x : th) x.join();
     }
 }
 
