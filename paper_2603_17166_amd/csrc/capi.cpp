@@ -155,8 +155,9 @@ struct ScopedDevFree {
 // of an order writes its own partial copy of F, which a second kernel adds in.
 // Ssyn is the largest such length for which the longest item costs at most a
 // third of the average work per wave slot (two waves per SIMD), as for the
-// adjoint; a plan whose longest order would get fewer than three segments is
-// not segmented.
+// adjoint, lengthened where needed to at most 33 segments per order (32
+// partial copies); a plan whose longest order would get fewer than three
+// segments is not segmented.
 // The items use two rings per lane (one when PSHT_LEG_R fixes one): with
 // the parallelism from the segments, the longer per-step work beats the one
 // ring per lane of the plain list of such plans (lmax 4096, 5-degree disc:
@@ -180,6 +181,9 @@ bool build_synth_segments(psht_plan_s &p, int ncu, const std::vector<int> &first
     const double slots = (double)std::max(ncu, 1) * 4 * 2;
     int Ssyn = S;
     while ((double)Ssyn * 2 <= total / slots / 3.0) Ssyn *= 2;
+    // at most 32 partial copies of F (a tiny cap at very high lmax would
+    // otherwise take hundreds, each as large as F, in the workspace)
+    while ((int64_t)33 * Ssyn < (int64_t)lmax + 1 - s) Ssyn *= 2;
     if (const char *e = getenv("PSHT_SYN_SEG")) {  // tuning runs: a power-of-two multiple of S, 0 for none
         const int v = atoi(e);
         if (v == 0) Ssyn = lmax + 1;

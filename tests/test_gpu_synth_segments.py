@@ -173,3 +173,28 @@ def test_segmented_multi_map_and_gradient_form(monkeypatch):
     assert d <= 1e-12
     p.close()
     plain.close()
+
+
+def test_segmented_parts_bounded(monkeypatch):
+    """A tiny cap at very high lmax: at most 32 partial copies of F, the rest as
+    for any segmented plan (plain work list, oracle)."""
+    lmax, spin, eps = 8192, 2, 1e-10
+    say("segmented synthesis, lmax %d, 0.5-degree cap" % lmax)
+    th, ph = syn.uniform_cap(2000, 0.5 * DEG, 13000)
+    p, plain = _plan(th, ph, lmax, spin, eps, "fp64", None, monkeypatch)
+    info = p.info
+    say("  syn_segment %d, syn_parts %d, mmax %d, Lmax %d" %
+        (info["syn_segment"], info["syn_parts"], info["mmax"], info["Lmax"]))
+    assert info["syn_segment"] > 0 and 1 <= info["syn_parts"] <= 32
+    assert 33 * info["syn_segment"] >= lmax + 1 - spin
+    a = syn.gaussian_alm(lmax, spin, 13100)
+    ad = dev(a)
+    f = p.synth(ad).cpu().numpy()
+    f0 = plain.synth(ad).cpu().numpy()
+    idx = np.sort(syn.rng(13200).choice(th.shape[0], 20, replace=False))
+    ref = oracle.synth(a, th[idx], ph[idx], lmax, spin)
+    err, d = rel_l2(f[idx], ref), rel_l2(f, f0)
+    say("  vs oracle %.3e, vs plain work list %.3e" % (err, d))
+    assert err <= 10 * eps and d <= 1e-12
+    p.close()
+    plain.close()
