@@ -535,6 +535,39 @@ def batched_maps(w, nmaps: int, steps: int, check_points: int, log) -> dict:
     return res
 
 
+def serial_gpu_time(srv, mix, log, reps: int = 5) -> dict:
+    """GPU time of the mix's requests, each kind run alone: `reps` launches
+    back to back on one stream of the server's resident plans, HIP events
+    around them.  The mix-weighted mean is the GPU work per request; its
+    inverse bounds the request rate of one GPU without overlap."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    per_kind, count = {}, {}
+    for key, op, data in mix:
+        count[(key, op)] = count.get((key, op), 0) + 1
+        if (key, op) in per_kind or key not in srv.plans:
+            continue
+        plan = srv.plans[key].handle
+        x = data.unsqueeze(0)
+        ws = torch.empty(max(1, plan.info["workspace_bytes_per_map"]), dtype=torch.uint8, device="cuda")
+        fn = plan.synth if op == "synth" else plan.adjoint
+        with torch.cuda.stream(stream):
+            fn(x, stream=stream, workspace=ws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn(x, stream=stream, workspace=ws)
+            e1.record(stream)
+        e1.synchronize()
+        per_kind[(key, op)] = e0.elapsed_time(e1) / reps
+    n = sum(c for k, c in count.items() if k in per_kind)
+    mean_ms = sum(per_kind[k] * c for k, c in count.items() if k in per_kind) / max(n, 1)
+    log("served: %.3f ms of GPU time per request (kinds alone), %.0f requests/s without overlap" %
+        (mean_ms, 1e3 / mean_ms))
+    return {"serial_gpu_ms_per_request": mean_ms, "gpu_bound_requests_per_s": 1e3 / mean_ms}
+
+
 def served(n_requests: int, load: float, log, single_fp64: int = 0) -> dict:
     """Served mix: discs of 2/5/10/20 deg, lmax 512..4096, spin 0/2, 50/50
     synth/adjoint, FP32 eps 1e-5.  With single_fp64 > 0, the first that many
@@ -601,6 +634,7 @@ def served(n_requests: int, load: float, log, single_fp64: int = 0) -> dict:
                "latency_ms_by_kind": {k: {"p50": round(percentile(v, 50), 3), "p99": round(percentile(v, 99), 3),
                                           "n": len(v)} for k, v in sorted(kinds.items())}})
     log("served at %.1fx saturation: p50 %.2f ms, p99 %.2f ms" % (load, st["p50_ms"], st["p99_ms"]))
+    st.update(serial_gpu_time(srv, mix, log))
     srv.close()
     if single_fp64 > 0:
         sub = raw_mix[:single_fp64]
