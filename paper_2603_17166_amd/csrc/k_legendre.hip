@@ -303,20 +303,20 @@ __device__ inline void synth_clear_scaled(const LegState<R, SPIN> &S, double *fp
 }
 
 // One work item of the synthesis with R rings per lane (the item holds at
-// most 64 R rings): the sums over the degrees l0 .. lmax of order m, where the
+// most 64 R rings): the sums over the degrees l0 .. lend of order m, where the
 // recurrence starts from the seed at l0 = max(m, s) (soff < 0) or from the
 // states stored for l0 (soff >= 0, see leg_init_stored), written to the F
 // layout at Fout.
 template <int R, bool SPIN>
-__device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, int l0, int lmax, int64_t soff,
+__device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, int l0, int lend, int64_t soff,
                                       const double4 *st_mu, const int2 *st_k, double *Fout,
                                       double4 (*sbuf)[2][kStage + 1]) {
     const int m = it.m, s = a.spin, lane = threadIdx.x;
-    if (l0 > lmax) return;
+    if (l0 > lend) return;
 
     const int64_t base = (int64_t)m * (2 * a.lmax + 1 - m) / 2;
     const double4 *T4 = a.coef + base;
-    sbuf[0][lane >> 5][lane & 31] = stage_entry_synth(a, T4, base, m, l0, lmax, lane);
+    sbuf[0][lane >> 5][lane & 31] = stage_entry_synth(a, T4, base, m, l0, lend, lane);
 
     LegState<R, SPIN> S;
     if (soff < 0) leg_init<R, SPIN>(a, it, lane, S);
@@ -328,12 +328,12 @@ __device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, int l
     __syncthreads();
 
     int slot = 0;
-    for (int c = l0; c <= lmax; c += kStage) {
-        const bool has_next = c + kStage <= lmax;
+    for (int c = l0; c <= lend; c += kStage) {
+        const bool has_next = c + kStage <= lend;
         double4 nv;
-        if (has_next) nv = stage_entry_synth(a, T4, base, m, c + kStage, lmax, lane);
+        if (has_next) nv = stage_entry_synth(a, T4, base, m, c + kStage, lend, lane);
         const double4 *sT = sbuf[slot][0], *sQ = sbuf[slot][1];
-        const int n = min(kStage, lmax + 1 - c);
+        const int n = min(kStage, lend + 1 - c);
         if (!scaled && has_next) {
             // Full chunk, every step advances, no lane scaled: no per-step guards.
             // The coefficients of step t + 1 are read while step t computes.
@@ -382,15 +382,15 @@ __device__ inline void leg_synth_item(const LegArgs &a, const LegItem &it, int l
             }
         } else for (int b = 0; b < n; b += 8) {
             const int e = min(b + 8, n);
-            const bool full = c + b + 8 <= lmax;  // all eight steps exist and advance
+            const bool full = c + b + 8 <= lend;  // all eight steps exist and advance
             if (scaled && !leg_live<R, SPIN>(S)) {
                 // no active ring in the double range yet: recurrence only
-                if (full) advance_steps<R, SPIN, true, 8>(S, sT, b, e, c, lmax);
-                else advance_steps<R, SPIN, false, 8>(S, sT, b, e, c, lmax);
+                if (full) advance_steps<R, SPIN, true, 8>(S, sT, b, e, c, lend);
+                else advance_steps<R, SPIN, false, 8>(S, sT, b, e, c, lend);
             } else if (full) {
                 synth_steps8<R, SPIN>(S, fpr, fpi, fmr, fmi, sT, sQ, b);
             } else {
-                synth_steps<R, SPIN>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lmax);
+                synth_steps<R, SPIN>(S, fpr, fpi, fmr, fmi, sT, sQ, b, e, c, lend);
             }
             if (scaled) {
                 synth_renorm<R, SPIN>(S, fpr, fpi, fmr, fmi);
