@@ -102,7 +102,8 @@ def stage_work(w, info) -> dict:
     }
 
 
-STAGE_KERNEL = {"leg_synth": ("psht::k_leg_synth<",), "leg_adj": ("psht::k_leg_adj_seg6<", "psht::k_leg_adj_seg4<"),
+STAGE_KERNEL = {"leg_synth": ("psht::k_leg_synth<", "psht::k_leg_synth_seg<"),
+                "leg_adj": ("psht::k_leg_adj_seg6<", "psht::k_leg_adj_seg4<"),
                 "theta_synth": ("psht::k_theta_synth<",), "theta_adj": ("psht::k_theta_adjoint<",),
                 "phi_synth": ("psht::k_phi_synth<",), "phi_adj": ("psht::k_phi_adjoint<",),
                 "interp": ("psht::k_interp<",), "spread": ("psht::k_spread<",)}
