@@ -49,6 +49,9 @@ def test_noalloc_matches_synth_two_calls(prec, eps):
         say("noalloc %s: lmax %d spin %d cap %g deg, %d points" % (prec, lmax, spin, rad, n))
         th, ph = syn.uniform_cap(n, rad * DEG, 9500 + lmax)
         plan = Plan(th, ph, lmax, spin, eps, prec)
+        # the lmax 256 plan takes the degree-segmented synthesis (partial copies
+        # of F in the scratch), the lmax 96 plan the plain work list
+        say("  synthesis segment %d, partial copies %d" % (plan.info["syn_segment"], plan.info["syn_parts"]))
         assert plan.info["workspace_bytes_per_map"] <= _lib.NOALLOC_SCRATCH_BYTES
         a = torch.as_tensor(syn.gaussian_alm(lmax, spin, 9600 + lmax), device="cuda")
         _both(plan, a, eps)
