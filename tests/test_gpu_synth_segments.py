@@ -198,3 +198,30 @@ def test_segmented_parts_bounded(monkeypatch):
     assert err <= 10 * eps and d <= 1e-12
     p.close()
     plain.close()
+
+
+def test_segmented_stage_workspace_errors():
+    """psht_stage_ex on a segmented plan: a workspace below workspace_bytes_per_map
+    is refused before any launch (the output keeps its contents); without a
+    workspace the stage runs the plain work list."""
+    from paper_2603_17166_amd import _lib
+    lmax, spin = 1024, 2
+    th, ph = syn.uniform_cap(1000, 2.0 * DEG, 13300)
+    p = Plan(th, ph, lmax, spin, 1e-10, "fp64")
+    assert p.info["syn_segment"] > 0
+    a = dev(syn.gaussian_alm(lmax, spin, 13400))
+    shape = (2 * p.info["mmax"] + 1, p.info["Lmax"] + 1)
+    out = torch.full(shape, 7.0 + 0j, dtype=torch.complex128, device="cuda")
+    small = torch.empty(p.info["workspace_bytes_per_map"] - 256, dtype=torch.uint8, device="cuda")
+    lib = _lib.load()
+    st = torch.cuda.current_stream().cuda_stream
+    code = lib.psht_stage_ex(p._h, _lib.STAGE_LEGENDRE_SYNTH, a.data_ptr(), out.data_ptr(), small.data_ptr(),
+                             small.numel(), st)
+    assert code == _lib.PSHT_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    assert bool(torch.all(out == 7.0))
+    code = lib.psht_stage_ex(p._h, _lib.STAGE_LEGENDRE_SYNTH, a.data_ptr(), out.data_ptr(), None, 0, st)
+    assert code == _lib.PSHT_OK
+    F0 = p.legendre_synth(a).cpu().numpy()
+    assert np.array_equal(out.cpu().numpy(), F0)
+    p.close()
