@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *theta, const 
     sbad[threadIdx.x] = bad;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
             smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
             sbad[threadIdx.x] += sbad[threadIdx.x + s];
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int n, int3
     part[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        int32_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
         __syncthreads();
         part[threadIdx.x] += v;
         __syncthreads();
