@@ -3,7 +3,6 @@ configuration bench.py times: the whole point set goes through the GPU, the
 oracle checks a seeded subsample (synthesis) or the adjoint of a map that is
 non-zero only on a seeded subsample (every coefficient compared)."""
 import math
-import sys
 
 import numpy as np
 import pytest

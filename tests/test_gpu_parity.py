@@ -265,7 +265,6 @@ def test_invalid_points_rejected():
 
 
 def test_workspace_too_small():
-    import ctypes
     th, ph = syn.uniform_cap(100, 10 * DEG, 8800)
     plan = Plan(th, ph, 32, 0, 1e-8)
     a = dev(syn.gaussian_alm(32, 0, 8900))
