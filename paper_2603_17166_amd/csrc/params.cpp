@@ -378,23 +378,53 @@ static bool leg_significant(int lmax, int s, int m, ld theta, ld tau, const Degr
 }
 
 // Largest m with a significant ring contribution (polar optimization: orders
-// well above lmax sin(theta) are irrelevant on the ring, Sec. II.A).
-static int ring_cutoff(int lmax, int s, ld theta, ld tau, const DegreeRoots &R) {
+// well above lmax sin(theta) are irrelevant on the ring, Sec. II.A), searched
+// from a guess: the neighbouring ring's cut-off, shifted by the change of
+// lmax sin(theta), lies within a few orders of the boundary, so a handful of
+// tests replace a bisection over [lmax sin(theta), lmax].
+static int ring_cutoff(int lmax, int s, ld theta, ld tau, const DegreeRoots &R, int guess) {
     if (theta == 0) return std::min(s, lmax);
-    int lo = (int)floorl(lmax * sinl(theta));
-    lo = std::max(0, std::min(lo, lmax));
-    while (lo > 0 && !leg_significant(lmax, s, lo, theta, tau, R)) lo /= 2;
-    if (!leg_significant(lmax, s, lo, theta, tau, R)) return std::min(s, lmax);
-    if (leg_significant(lmax, s, lmax, theta, tau, R)) return lmax;
-    int hi = lmax;  // lo significant, hi not
+    auto sig = [&](int m) { return leg_significant(lmax, s, m, theta, tau, R); };
+    // bracket the boundary by steps doubling away from the guess: lo significant
+    // (or -1), hi not (or lmax + 1); then bisect
+    int lo, hi, g = std::max(0, std::min(guess, lmax));
+    if (sig(g)) {
+        lo = g;
+        for (int step = 1;; step *= 2) {
+            const int t = lo + step;
+            if (t > lmax) {
+                hi = lmax + 1;
+                break;
+            }
+            if (!sig(t)) {
+                hi = t;
+                break;
+            }
+            lo = t;
+        }
+    } else {
+        hi = g;
+        for (int step = 1;; step *= 2) {
+            const int t = hi - step;
+            if (t < 0) {
+                lo = -1;
+                break;
+            }
+            if (sig(t)) {
+                lo = t;
+                break;
+            }
+            hi = t;
+        }
+    }
     while (hi - lo > 1) {
-        int mid = lo + (hi - lo) / 2;
-        if (leg_significant(lmax, s, mid, theta, tau, R))
+        const int mid = lo + (hi - lo) / 2;
+        if (sig(mid))
             lo = mid;
         else
             hi = mid;
     }
-    return lo;
+    return lo < 0 ? std::min(s, lmax) : lo;
 }
 
 // ------------------------------------------- error predictor (Sec. II.D)
@@ -680,12 +710,23 @@ bool geometry_compute(Geometry &g, int lmax, int spin, double theta_star, double
     if (with_cutoffs) {
         ld tau = (ld)(kPolarTauRel * eps);
         const DegreeRoots roots(lmax);
+        // contiguous runs of rings per thread, each ring seeded with its
+        // neighbour's cut-off (the first of a run with lmax sin(theta) plus the
+        // usual margin of the transition, about 8 (lmax sin(theta))^(1/3))
         unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const int run = (g.nring + (int)nt - 1) / (int)nt;
+        auto est = [&](int j) { return (ld)lmax * fabsl(sinl((ld)g.ring_theta[j])); };
         std::vector<std::thread> th;
         for (unsigned t = 0; t < nt; ++t)
             th.emplace_back([&, t]() {
-                for (int j = (int)t; j < g.nring; j += (int)nt)
-                    g.ring_mmax[j] = ring_cutoff(lmax, spin, (ld)g.ring_theta[j], tau, roots);
+                const int j0 = (int)t * run, j1 = std::min(g.nring, j0 + run);
+                int prev = -1;
+                for (int j = j0; j < j1; ++j) {
+                    const ld e = est(j);
+                    const int guess = prev < 0 ? (int)(e + 8 * cbrtl(e)) : prev + (int)lroundl(e - est(j - 1));
+                    g.ring_mmax[j] = ring_cutoff(lmax, spin, (ld)g.ring_theta[j], tau, roots, guess);
+                    prev = g.ring_mmax[j];
+                }
             });
         for (auto &x : th) x.join();
     }
