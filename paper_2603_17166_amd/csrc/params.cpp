@@ -851,7 +851,8 @@ void leg_table_host(LegTable &t, int lmax, int s) {
         for (int l = l0; l <= lmax; ++l) {
             double *e = &t.h_coef[4 * (base + l)];
             if (l < lmax) {
-                const ld A = a[l] * P[l] / P[l + 1], B = b[l] * P[l] / P[l + 1];
+                const ld r = P[l] / P[l + 1];
+                const ld A = a[l] * r, B = b[l] * r;
                 e[0] = (double)(-A);
                 e[1] = (double)(A + B);
                 e[2] = (double)(A - B);
