@@ -569,7 +569,8 @@ def serial_gpu_time(srv, mix, log, reps: int = 5) -> dict:
     return {"serial_gpu_ms_per_request": mean_ms, "gpu_bound_requests_per_s": 1e3 / mean_ms}
 
 
-def served(n_requests: int, load: float, log, single_fp64: int = 0, max_batch: int = 8) -> dict:
+def served(n_requests: int, load: float, log, single_fp64: int = 0, max_batch: int = 8,
+           policy: str = "sjf") -> dict:
     """Served mix: discs of 2/5/10/20 deg, lmax 512..4096, spin 0/2, 50/50
     synth/adjoint, FP32 eps 1e-5.  With single_fp64 > 0, the first that many
     requests of the same mix are also run one at a time (no batching, no
@@ -605,7 +606,7 @@ def served(n_requests: int, load: float, log, single_fp64: int = 0, max_batch: i
             out.append((key, op, alms[(lmax, spin)] if op == "synth" else maps[radius]))
         return out
 
-    srv = Server(ex, memory_budget=96 << 30, n_slots=4, max_batch=max_batch)
+    srv = Server(ex, memory_budget=96 << 30, n_slots=4, max_batch=max_batch, policy=policy)
     t0 = time.perf_counter()
     combos = [(r, l, s, op, 0) for r in syn.SERVED_RADII for l in syn.SERVED_LMAX for s in syn.SERVED_SPINS
               for op in ("synth", "adjoint")]
@@ -628,7 +629,8 @@ def served(n_requests: int, load: float, log, single_fp64: int = 0, max_batch: i
     for r in reqs:
         if r.error is None:
             kinds.setdefault("%s-l%d-%s" % (r.key.patch, r.key.lmax, r.op), []).append(r.latency * 1e3)
-    st.update({"load": load, "arrival_rate_per_s": rate, "saturation_requests_per_s": sat,
+    st.update({"policy": policy, "max_batch": max_batch, "load": load, "arrival_rate_per_s": rate,
+               "saturation_requests_per_s": sat,
                "points_per_s": pts / span, "saturation_points_per_s": pts / secs, "batches": srv.n_batches,
                "max_concurrent": srv.max_concurrent, "plans_resident": len(srv.plans),
                "resident_gb": srv.resident / 1e9, "errors": sum(1 for r in reqs if r.error),
@@ -707,6 +709,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads and the served mix")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--serve-policy", default="sjf", choices=("fifo", "sjf"),
+                    help="admission order: oldest first, or cheapest plan first with an age limit")
     ap.add_argument("--serve-max-batch", type=int, default=8,
                     help="requests of one kind per launch (8: the maps of one batched Legendre pass)")
     ap.add_argument("--serve-fp64-single", type=int, default=300,
@@ -741,7 +745,7 @@ def main() -> int:
         return 0
     if args.served_only:
         print(json.dumps(served(args.serve_requests, args.serve_load, log, args.serve_fp64_single,
-                                args.serve_max_batch)), flush=True)
+                                args.serve_max_batch, args.serve_policy)), flush=True)
         return 0
     if args.full_sky_only:
         print(json.dumps(full_sky_speedup([syn.spt_like(2048), syn.spt_fine("fp64")], 3, log)), flush=True)
@@ -804,7 +808,7 @@ def main() -> int:
         line["lmax_rules_disc10"] = plan_rules(syn.served_disc(10.0, 4096, 2), 5, log)
         line["patch_frame"] = patch_frame(w64.lmax, w64.npoints, 3, log)
         line["served"] = served(args.serve_requests, args.serve_load, log, args.serve_fp64_single,
-                                args.serve_max_batch)
+                                args.serve_max_batch, args.serve_policy)
         if "served_vs_fp64_single" in line["served"]:
             line["served_vs_fp64_single"] = line["served"]["served_vs_fp64_single"]
     print(json.dumps(line), flush=True)

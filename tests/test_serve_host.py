@@ -127,8 +127,8 @@ def test_memory_budget_never_exceeded_and_lru_eviction():
     seen = []
     orig = srv._admit_head
 
-    def admit():
-        ok = orig()
+    def admit(head):
+        ok = orig(head)
         seen.append(srv._used())
         return ok
     srv._admit_head = admit
@@ -262,3 +262,53 @@ def test_budget_rechecked_after_creation():
     srv.run_until_idle()
     assert srv.plans_evicted == 1 and set(ex.live_plans) == {K("b")}
     assert srv._used() == 650 and srv.shared == {("tab", 64): [50, 1]}
+
+
+class CostExecutor(FakeExecutor):
+    """FakeExecutor that also reports each plan's cost, as the device executor does."""
+
+    def cost_estimate(self, h, op):
+        return self.cost(h, op, 1)
+
+
+def test_sjf_admits_cheapest_first():
+    """One slot: after the first batch, the cheap plan's request goes before
+    the older expensive ones (their plans are known from earlier requests)."""
+    c = Clock()
+    ex = CostExecutor(c, cost=lambda k, op, n: 10.0 if k.patch == "big" else 1.0)
+    srv = Server(ex, memory_budget=10_000, n_slots=1, max_batch=1, clock=c, policy="sjf", max_wait=100.0)
+    warm = [srv.submit(K("big"), "synth", 0), srv.submit(K("small"), "synth", 1)]
+    srv.run_until_idle()
+    assert all(r.done for r in warm)
+    t0 = c.t
+    b1 = srv.submit(K("big"), "synth", 2, t_arrival=t0)
+    b2 = srv.submit(K("big"), "synth", 3, t_arrival=t0)
+    s1 = srv.submit(K("small"), "synth", 4, t_arrival=t0)
+    srv.run_until_idle()
+    assert s1.t_admit < b1.t_admit < b2.t_admit  # cheapest first, then in arrival order
+    fifo = Server(CostExecutor(c), memory_budget=10_000, n_slots=1, max_batch=1, clock=c)
+    assert fifo.policy == "fifo"
+
+
+def test_sjf_starvation_guard():
+    """A request that waited past max_wait is admitted before cheaper ones."""
+    c = Clock()
+    ex = CostExecutor(c, cost=lambda k, op, n: 10.0 if k.patch == "big" else 1.0)
+    srv = Server(ex, memory_budget=10_000, n_slots=1, max_batch=1, clock=c, policy="sjf", max_wait=5.0)
+    for p in ("big", "small"):
+        srv.submit(K(p), "synth", 0)
+    srv.run_until_idle()
+    t0 = c.t
+    big = srv.submit(K("big"), "synth", 1, t_arrival=t0)
+    smalls = [srv.submit(K("small"), "synth", 10 + i, t_arrival=t0 + 0.5 * i) for i in range(20)]
+    srv.run_until_idle()
+    # the big request waits at most about max_wait plus one running batch, not for all 20 small ones
+    assert big.t_admit - t0 <= 5.0 + 1.0 + 1e-9
+    assert sum(1 for r in smalls if r.t_admit < big.t_admit) < 20
+
+
+def test_policy_arguments_checked():
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(Clock()), memory_budget=10, policy="lifo")
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(Clock()), memory_budget=10, policy="sjf", max_wait=0.0)
