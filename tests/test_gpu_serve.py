@@ -15,7 +15,8 @@ torch = pytest.importorskip("torch")
 
 from paper_2603_17166_amd import synthetic as syn
 from paper_2603_17166_amd.plan import Plan
-from paper_2603_17166_amd.serve import PlanKey, Server, TorchExecutor, latency_stats, poisson_arrivals, run_open_loop
+from paper_2603_17166_amd.serve import (PlanKey, Server, TorchExecutor, latency_stats, poisson_arrivals,
+                                        run_closed_loop, run_open_loop)
 
 pytestmark = pytest.mark.gpu
 EPS = 1e-5
@@ -131,3 +132,18 @@ def test_served_mix_equals_alone_and_oracle():
     say("served vs stored oracle: %d (radius, lmax, spin, op) checked, worst rel L2 %.2e" % (len(checked), worst_o))
     assert len(checked) == len(syn.SERVED_RADII) * len(syn.SERVED_LMAX) * len(syn.SERVED_SPINS) * 2
     srv.close()
+
+    # the same requests once more, all queued at once, admitted cheapest plan
+    # first: the order changes, the results do not
+    ex2 = TorchExecutor(n_slots=4)
+    for r, (th, ph) in patches.items():
+        ex2.add_patch("disc%g" % r, th, ph)
+    srv2 = Server(ex2, memory_budget=64 << 30, n_slots=4, max_batch=8, policy="sjf")
+    reqs2, _ = run_closed_loop(srv2, specs)
+    torch.cuda.synchronize()
+    assert all(r.error is None for r in reqs2)
+    assert len(srv2.costs) == 2 * len({k for k, _, _ in specs}) and all(c > 0 for c in srv2.costs.values())
+    worst2 = max(_rel(r.result, ref) for r, ref in zip(reqs2, alone))
+    say("cheapest-first served vs alone: worst rel L2 %.2e" % worst2)
+    assert worst2 <= 10 * EPS
+    srv2.close()
